@@ -1,0 +1,201 @@
+/*
+ * libhigs: MI355X (gfx950) implementation of the forward frame path of
+ * HiGS, "A Hierarchical Rendering Architecture for Real-Time 3D Gaussian
+ * Splatting" (Pajak, Bisson, Lima; arXiv 2606.00352).
+ *
+ * The path, in stage order (each stage is a set of HIP kernels):
+ *   higs_project  - per-gaussian EWA projection with degree<=3 SH colour
+ *                   (sec. 4.2, Projection and SH evaluation).
+ *   higs_bin_sort - (macro-tile, depth) pair emission over 64x32-pixel
+ *                   macro-tiles (sec. 3.2 / sec. 4.3) and their sort by
+ *                   (macro-tile, depth) with ties broken by gaussian id
+ *                   (sec. 3.3 / sec. 4.4).
+ *   higs_batch    - split of each macro-tile's sorted list into batches of
+ *                   at most B_r gaussians, one processing unit each
+ *                   (sec. 3.1, Macro-tile hierarchy and work decomposition).
+ *   higs_raster   - per-unit rasterisation over the 8x8 render tiles of the
+ *                   macro-tile (sec. 3.4, Algorithms 1 and 2) and the
+ *                   post-blend merge of the batch partials with Eq. 1.
+ *   higs_render   - all of the above in one call.
+ *
+ * Conventions shared by every entry point:
+ *   - Array arguments are DEVICE pointers to contiguous row-major float32
+ *     unless stated otherwise; the caller owns them and they must stay valid
+ *     until the work queued on `stream` has finished.  The library never
+ *     frees caller memory.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *     enqueues work on it and returns without waiting, except
+ *     higs_get_counts and higs_debug_copy, which synchronise the stream of
+ *     the last call.
+ *   - A context owns every intermediate buffer, sized at creation for the
+ *     capacities given there; intermediates stay valid until the next call
+ *     that rewrites them.  A context is used from one host thread and one
+ *     stream at a time.
+ *   - Return value: HIGS_OK (0) or a negative HIGS_E_* code; higs_error_string
+ *     turns it into text.  Data-dependent capacity overflow (more pairs or
+ *     batches than the context holds) cannot be known when the work is
+ *     enqueued: it is recorded on the device, the outputs of that frame are
+ *     then undefined, and higs_get_counts reports it (overflow bits) so the
+ *     caller can grow the context and render again.
+ *   - Gaussians with a non-finite mean, scale, rotation or opacity, a zero
+ *     quaternion, camera-space depth <= near_z, opacity below 1/255, or a
+ *     non-positive-definite 2D covariance are culled (not an error).
+ */
+#ifndef HIGS_H
+#define HIGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HIGS_OK 0
+#define HIGS_E_INVALID (-1)     /* null pointer, negative size, bad parameter */
+#define HIGS_E_NOMEM (-2)       /* device allocation failed */
+#define HIGS_E_CAPACITY (-3)    /* a host-known size exceeds the context */
+#define HIGS_E_HIP (-4)         /* a HIP runtime call failed */
+#define HIGS_E_UNSUPPORTED (-5) /* tile shape or SH degree not implemented */
+#define HIGS_E_STATE (-6)       /* stage called before the one it depends on */
+
+/* Overflow bits reported by higs_get_counts. */
+#define HIGS_OVF_PAIRS 1u   /* more (macro-tile, gaussian) pairs than max_pairs */
+#define HIGS_OVF_BATCHES 2u /* more batches than max_batches */
+#define HIGS_ERR_STALL 0x80000000u /* internal: a sort look-back timed out (frame invalid) */
+
+typedef struct higs_ctx higs_ctx;
+
+/* Method parameters (sec. 3.1 and sec. 5.3 of the paper).  Only the paper's
+ * tile shape is implemented: tile_px = 8, mt_tiles_x = 8, mt_tiles_y = 4. */
+typedef struct {
+  int32_t tile_px;    /* render tile edge in pixels: 8 */
+  int32_t mt_tiles_x; /* render tiles per macro-tile, horizontally: 8 */
+  int32_t mt_tiles_y; /* render tiles per macro-tile, vertically: 4 */
+  int32_t batch_cap;  /* B_r, gaussians per processing unit, 1..1024 (1024) */
+  int32_t sh_degree;  /* 0..3 (3); sh arrays hold (sh_degree+1)^2 x 3 floats */
+  float alpha_max;    /* clamp of alpha (0.99) */
+  float t_eps;        /* compositing stops once T < t_eps (1e-4) */
+  float near_z;       /* cull at camera-space depth <= near_z (0.2) */
+  float dilation;     /* added to the 2D covariance diagonal (0.3) */
+} higs_params;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward).  Pixel (i, j)
+ * has its centre at (i + 0.5, j + 0.5).  HOST memory. */
+typedef struct {
+  int32_t width, height;   /* image size in pixels, >= 1 */
+  float fx, fy, cx, cy;    /* focal lengths and principal point, pixels */
+  float world_to_cam[12];  /* row-major [R | t]: x_cam = R x_world + t */
+  float background[3];     /* added as T * background to the composite */
+} higs_camera;
+
+/* Sizes of the last frame; filled by higs_get_counts. */
+typedef struct {
+  int64_t n_gaussians; /* gaussians submitted to higs_project */
+  int64_t n_visible;   /* gaussians with at least one macro-tile pair */
+  int64_t n_pairs;     /* (macro-tile, gaussian) pairs emitted */
+  int64_t n_batches;   /* (macro-tile, batch) processing units */
+  uint32_t overflow;   /* HIGS_OVF_* bits */
+} higs_counts;
+
+/* Writes the paper's defaults into *p. */
+void higs_default_params(higs_params* p);
+
+/* Creates a context on HIP device `device` with every intermediate sized for
+ * at most max_gaussians gaussians, max_pairs pairs, max_batches processing
+ * units and max_width x max_height images.  *out receives the handle.
+ * Returns HIGS_E_UNSUPPORTED for a tile shape other than 8x8 / 8x4 or
+ * sh_degree > 3, HIGS_E_INVALID for non-positive capacities or a batch_cap
+ * outside 1..1024, HIGS_E_NOMEM if the device memory is not there. */
+int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians,
+                    int64_t max_pairs, int64_t max_batches, int32_t max_width,
+                    int32_t max_height, higs_ctx** out);
+
+/* Releases the context and its device memory (synchronises its stream). */
+int higs_ctx_destroy(higs_ctx* ctx);
+
+/* Stage 1: projects n gaussians for `cam` (sec. 4.2).  Inputs (device):
+ *   means [n,3], scales [n,3] (linear), quats [n,4] as (w,x,y,z), any norm,
+ *   opacities [n] (in [0,1]), sh [n, (sh_degree+1)^2, 3].
+ * The camera is copied; later stages of the frame use it.  n may be 0.
+ * HIGS_E_CAPACITY if n > max_gaussians or the image exceeds max size. */
+int higs_project(higs_ctx* ctx, int64_t n, const float* means, const float* scales,
+                 const float* quats, const float* opacities, const float* sh,
+                 const higs_camera* cam, void* stream);
+
+/* Stage 2: emits every (macro-tile, gaussian) pair whose opacity-level
+ * ellipse {q <= 2 ln(255 o)} meets the macro-tile's rectangle (sec. 3.2) in
+ * gaussian-id order, and sorts them by (macro-tile, float32 depth bits,
+ * gaussian id) (sec. 3.3).  Needs higs_project of the same frame. */
+int higs_bin_sort(higs_ctx* ctx, void* stream);
+
+/* Stage 3: per macro-tile, ceil(n / batch_cap) batches in (macro-tile,
+ * batch) order (sec. 3.1).  Needs higs_bin_sort of the same frame. */
+int higs_batch(higs_ctx* ctx, void* stream);
+
+/* Stage 4: rasterises every processing unit from (C, T) = (0, 1) with
+ * front-to-back blending, alpha = min(alpha_max, o exp(-q/2)), skipping
+ * alpha < 1/255 and stopping once T < t_eps, then merges the partials of each
+ * render tile in batch order with Eq. 1 (C = C0 + T0 C1 + T0 T1 C2 + ...,
+ * stopping once the product of T drops below t_eps).  Outputs (device):
+ *   image [height, width, 3] = C + T * background;
+ *   T_out [height, width] final transmittance, or NULL.
+ * Needs higs_batch of the same frame. */
+int higs_raster(higs_ctx* ctx, float* image, float* T_out, void* stream);
+
+/* All four stages for one frame. */
+int higs_render(higs_ctx* ctx, int64_t n, const float* means, const float* scales,
+                const float* quats, const float* opacities, const float* sh,
+                const higs_camera* cam, float* image, float* T_out, void* stream);
+
+/* Synchronises the stream of the last call and reports the frame's sizes. */
+int higs_get_counts(higs_ctx* ctx, higs_counts* out);
+
+/* Intermediate buffers that higs_debug_copy can read back (tests). */
+#define HIGS_DBG_PROJ 1     /* float32 [8][n]: mx, my, a, b, c, tau, key bits, count bits
+                               (rows of culled gaussians: key = 0, count = 0, rest undefined) */
+#define HIGS_DBG_RECORDS 2  /* float32 [n][12]: mx, my, l0, l1, l2, o, r, g, b, tau, 0, 0
+                               (defined for gaussians with count > 0) */
+#define HIGS_DBG_PAIRS 3    /* uint64 keys [n_pairs] then uint32 ids [n_pairs], emission order
+                               (needs HIGS_DEBUG_KEEP_PAIRS); key = macro-tile << 32 | depth bits */
+#define HIGS_DBG_SORTED 4   /* same layout, sorted */
+#define HIGS_DBG_MT_OFFSETS 5 /* uint32 [n_macro_tiles + 1]: first sorted pair of each macro-tile */
+#define HIGS_DBG_BATCHES 6  /* uint32 [n_batches][3]: macro-tile, start, length */
+#define HIGS_DBG_ACTIVE 7   /* uint32 [n_batches]: bit t = render tile t written by the unit */
+#define HIGS_DBG_PARTIALS 8 /* float32 [n_batches][32][64][4]: R, G, B, T per pixel, valid
+                               where the active bit is set; pixel p of tile t sits at
+                               (t % 8 * 8 + p % 8, t / 8 * 8 + p / 8) in the macro-tile */
+
+/* Debug options: HIGS_DEBUG_KEEP_PAIRS keeps a copy of the emitted pairs
+ * before the sort (allocates max_pairs * 12 bytes on first use) so that
+ * HIGS_DBG_PAIRS can read them back. */
+#define HIGS_DEBUG_KEEP_PAIRS 1
+int higs_set_debug(higs_ctx* ctx, int flags);
+
+/* Copies `bytes` bytes of buffer `which` (HIGS_DBG_*) into HOST memory
+ * `host_dst`, after synchronising.  HIGS_E_INVALID if `bytes` exceeds the
+ * buffer's current content. */
+int higs_debug_copy(higs_ctx* ctx, int which, void* host_dst, size_t bytes);
+
+/* Per-kernel device times of the last frame, measured with HIP events
+ * recorded on the frame's stream around each kernel group when timing is on
+ * (off by default).  ms[HIGS_TIMER_*] in milliseconds; synchronises. */
+#define HIGS_TIMER_PROJECT 0 /* projection + SH + per-gaussian pair counts */
+#define HIGS_TIMER_SCAN 1    /* exclusive scan of the pair counts */
+#define HIGS_TIMER_FILL 2    /* pair emission */
+#define HIGS_TIMER_SORT 3    /* all radix-sort kernels */
+#define HIGS_TIMER_BATCH 4   /* macro-tile offsets + batch table */
+#define HIGS_TIMER_RASTER 5  /* per-unit rasteriser */
+#define HIGS_TIMER_MERGE 6   /* post-blend merge */
+#define HIGS_NUM_TIMERS 7
+int higs_set_timing(higs_ctx* ctx, int on);
+int higs_get_timers(higs_ctx* ctx, float ms[HIGS_NUM_TIMERS]);
+
+/* Static text for a return code. */
+const char* higs_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HIGS_H */

@@ -68,7 +68,10 @@ class Params:
     sh_degree: int = 3
 
     def c(self) -> _Params:
-        return _Params(self.near_z, self.alpha_min, self.alpha_max, self.t_eps, self.dilation,
+        # near_z, alpha_max, t_eps and dilation cross the library interface as
+        # float32, as the camera does: the oracle takes the same float values
+        f = lambda v: float(np.float32(v))
+        return _Params(f(self.near_z), self.alpha_min, f(self.alpha_max), f(self.t_eps), f(self.dilation),
                        self.batch_cap, self.sh_degree)
 
 

@@ -1,0 +1,102 @@
+// Stage 3: macro-tile segments and the batch table (sec. 3.1: a macro-tile
+// holding n gaussians spawns ceil(n / B_r) processing units).
+//
+// `mt_offsets_kernel`: one wave per macro-tile finds the first sorted pair of
+// that macro-tile with a 64-ary search (each step probes 64 evenly spaced
+// keys and keeps the bracket where the predicate flips), so a 10^7-pair list
+// takes four dependent loads per macro-tile.
+// `batch_table_kernel` (one workgroup): batches per macro-tile, their
+// exclusive scan (first batch of every macro-tile) and the (macro-tile,
+// start, length) rows in (macro-tile, batch) order.
+#include "higs_internal.h"
+
+namespace higs {
+
+constexpr int kOffThreads = 256;
+__global__ void __launch_bounds__(kOffThreads)
+mt_offsets_kernel(int n_mt, const uint64_t* __restrict__ k0, const uint64_t* __restrict__ k1,
+                  const DeviceCounters* __restrict__ dc, uint32_t* __restrict__ mt_off) {
+  const int m = blockIdx.x * (kOffThreads / 64) + (threadIdx.x >> 6);
+  if (m > n_mt) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t* __restrict__ keys = dc->sort_final ? k1 : k0;
+  const uint64_t target = (uint64_t)m << 32;
+  uint32_t lo = 0, hi = dc->n_pairs;  // answer in [lo, hi]
+  while (hi - lo > 64) {
+    const uint32_t step = (hi - lo + 63) / 64;
+    const uint32_t p = lo + (uint32_t)lane * step;
+    const bool below = p < hi && keys[p] < target;
+    const uint32_t c = (uint32_t)__popcll(__ballot(below));
+    if (c == 0) {
+      hi = lo;
+    } else {
+      const uint32_t nlo = lo + (c - 1) * step + 1;
+      const uint32_t nhi = lo + c * step;
+      lo = nlo;
+      hi = nhi < hi ? nhi : hi;
+    }
+  }
+  const uint32_t p = lo + (uint32_t)lane;
+  const bool below = p < hi && keys[p] < target;
+  const uint32_t c = (uint32_t)__popcll(__ballot(below));
+  if (lane == 0) mt_off[m] = lo + c;
+}
+
+constexpr int kBtThreads = 1024;
+__global__ void __launch_bounds__(kBtThreads)
+batch_table_kernel(int n_mt, uint32_t cap, uint32_t max_batches, const uint32_t* __restrict__ mt_off,
+                   DeviceCounters* __restrict__ dc, uint32_t* __restrict__ batch_first,
+                   uint32_t* __restrict__ tab) {
+  __shared__ uint32_t wave_tot[kBtThreads / 64];
+  const int per = (n_mt + kBtThreads - 1) / kBtThreads;
+  const int m0 = threadIdx.x * per;
+  const int m1 = min(m0 + per, n_mt);
+  uint32_t mine = 0;
+  for (int m = m0; m < m1; ++m) mine += (mt_off[m + 1] - mt_off[m] + cap - 1) / cap;
+  uint32_t v = mine;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = __shfl_up(v, off, 64);
+    if (lane >= off) v += o;
+  }
+  if (lane == 63) wave_tot[wave] = v;
+  __syncthreads();
+  uint32_t run = v - mine;
+  for (int w = 0; w < wave; ++w) run += wave_tot[w];
+  for (int m = m0; m < m1; ++m) {
+    const uint32_t off = mt_off[m];
+    const uint32_t len = mt_off[m + 1] - off;
+    const uint32_t nb = (len + cap - 1) / cap;
+    batch_first[m] = run;
+    for (uint32_t b = 0; b < nb; ++b) {
+      const uint32_t idx = run + b;
+      if (idx < max_batches) {
+        tab[3 * idx + 0] = (uint32_t)m;
+        tab[3 * idx + 1] = off + b * cap;
+        tab[3 * idx + 2] = min(cap, len - b * cap);
+      }
+    }
+    run += nb;
+  }
+  if (threadIdx.x == kBtThreads - 1) {
+    batch_first[n_mt] = run;
+    dc->n_batches_total = run;
+    dc->n_batches = run < max_batches ? run : max_batches;
+    if (run > max_batches) dc->overflow |= HIGS_OVF_BATCHES;
+  }
+}
+
+hipError_t launch_batch(int n_mt, uint32_t batch_cap, uint32_t max_batches, const uint64_t* const* keys2,
+                        DeviceCounters* dc, uint32_t* mt_off, uint32_t* batch_first,
+                        uint32_t* batch_tab, hipStream_t s) {
+  const int waves = n_mt + 1;
+  const int blocks = (waves + (kOffThreads / 64) - 1) / (kOffThreads / 64);
+  hipLaunchKernelGGL(mt_offsets_kernel, dim3(blocks), dim3(kOffThreads), 0, s, n_mt, keys2[0],
+                     keys2[1], dc, mt_off);
+  hipLaunchKernelGGL(batch_table_kernel, dim3(1), dim3(kBtThreads), 0, s, n_mt, batch_cap,
+                     max_batches, mt_off, dc, batch_first, batch_tab);
+  return hipGetLastError();
+}
+
+}  // namespace higs

@@ -1,0 +1,140 @@
+// Stage 2a: (macro-tile, gaussian) pair emission (sec. 3.2 and sec. 4.3:
+// count, prefix sum, fill).
+//
+// The per-gaussian counts come from the projection kernel.  `scan_kernel`
+// (one workgroup) turns the per-block sums into exclusive block offsets and
+// the frame's pair total; `fill_kernel` re-runs the intersection of each
+// gaussian from the stored float32 fields (so it takes the count pass's exact
+// decisions), scans the counts inside the block with wave prefix sums, and
+// writes pairs (key = macro-tile << 32 | float32 depth bits, value = gaussian
+// id) in gaussian-id order, macro-tiles ascending within a gaussian.  Waves
+// whose 64 gaussians are all invisible skip the fields entirely (ballot).
+#include "higs_internal.h"
+#include "predicate.h"
+
+namespace higs {
+
+__global__ void clear_kernel(DeviceCounters* dc, uint32_t* hist, int n_hist) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(dc);
+  const int nw = (int)(sizeof(DeviceCounters) / 4);
+  for (int k = threadIdx.x; k < nw; k += blockDim.x) w[k] = 0;
+  for (int k = threadIdx.x; k < n_hist; k += blockDim.x) hist[k] = 0;
+}
+
+hipError_t launch_clear(DeviceCounters* dc, uint32_t* hist, int n_hist, hipStream_t s) {
+  hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(256), 0, s, dc, hist, n_hist);
+  return hipGetLastError();
+}
+
+// Inclusive wave-wide prefix sum of 64 lanes.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = __shfl_up(v, off, 64);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+
+// One workgroup of 1024 threads: exclusive scan of the per-block (pairs,
+// visible) sums in place; writes the frame totals.
+constexpr int kScanThreads = 1024;
+__global__ void __launch_bounds__(kScanThreads)
+scan_kernel(uint32_t n_blocks, uint32_t* __restrict__ sums, uint32_t max_pairs,
+            DeviceCounters* __restrict__ dc) {
+  __shared__ uint32_t wave_tot[2][kScanThreads / 64];
+  const uint32_t per = (n_blocks + kScanThreads - 1) / kScanThreads;
+  const uint32_t b0 = threadIdx.x * per;
+  const uint32_t b1 = min(b0 + per, n_blocks);
+  uint32_t s_pairs = 0, s_vis = 0;
+  for (uint32_t b = b0; b < b1; ++b) {
+    s_pairs += sums[2 * b];
+    s_vis += sums[2 * b + 1];
+  }
+  const uint32_t ip = wave_incl_scan(s_pairs);
+  const uint32_t iv = wave_incl_scan(s_vis);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 63) {
+    wave_tot[0][wave] = ip;
+    wave_tot[1][wave] = iv;
+  }
+  __syncthreads();
+  uint32_t base_p = 0, base_v = 0;
+  for (int w = 0; w < wave; ++w) {
+    base_p += wave_tot[0][w];
+    base_v += wave_tot[1][w];
+  }
+  uint32_t run = base_p + ip - s_pairs;
+  for (uint32_t b = b0; b < b1; ++b) {
+    const uint32_t v = sums[2 * b];
+    sums[2 * b] = run;
+    run += v;
+  }
+  if (threadIdx.x == kScanThreads - 1) {
+    const uint32_t total = base_p + ip;
+    dc->n_pairs_total = total;
+    dc->n_pairs = total < max_pairs ? total : max_pairs;
+    dc->n_visible = base_v + iv;
+    if (total > max_pairs) dc->overflow |= HIGS_OVF_PAIRS;
+  }
+}
+
+hipError_t launch_scan(int64_t n, const uint32_t* cnt, uint32_t* block_sums, uint32_t max_pairs,
+                       DeviceCounters* dc, hipStream_t s) {
+  (void)cnt;
+  const uint32_t n_blocks = (uint32_t)((n + kProjBlock - 1) / kProjBlock);
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, s, n_blocks, block_sums,
+                     max_pairs, dc);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kProjBlock)
+fill_kernel(int64_t n, CamArgs cam, const float* __restrict__ f_mx, const float* __restrict__ f_my,
+            const float* __restrict__ f_a, const float* __restrict__ f_b,
+            const float* __restrict__ f_c, const float* __restrict__ f_tau,
+            const uint32_t* __restrict__ f_key, const uint32_t* __restrict__ f_cnt,
+            const uint32_t* __restrict__ block_offsets, uint32_t max_pairs,
+            uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  __shared__ uint32_t wave_tot[kProjBlock / 64];
+  const int64_t i = (int64_t)blockIdx.x * kProjBlock + threadIdx.x;
+  const uint32_t cnt = i < n ? f_cnt[i] : 0u;
+  const uint32_t incl = wave_incl_scan(cnt);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 63) wave_tot[wave] = incl;
+  __syncthreads();
+  if (__ballot(cnt > 0) == 0) return;  // whole wave invisible
+  uint32_t base = block_offsets[2 * blockIdx.x];
+  for (int w = 0; w < wave; ++w) base += wave_tot[w];
+  if (cnt == 0) return;
+  uint32_t at = base + incl - cnt;
+  BinFields f;
+  f.mx = f_mx[i];
+  f.my = f_my[i];
+  f.a = f_a[i];
+  f.b = f_b[i];
+  f.c = f_c[i];
+  f.tau = f_tau[i];
+  const uint64_t depth = (uint64_t)f_key[i];
+  const uint32_t gid = (uint32_t)i;
+  visit_macro_tiles(f, cam.width, cam.height, cam.n_mt_x, cam.n_mt_y, [&](uint32_t mt) {
+    if (at < max_pairs) {
+      keys[at] = ((uint64_t)mt << 32) | depth;
+      vals[at] = gid;
+    }
+    ++at;
+  });
+}
+
+hipError_t launch_fill(int64_t n, CamArgs cam, const float* f_mx, const float* f_my,
+                       const float* f_a, const float* f_b, const float* f_c, const float* f_tau,
+                       const uint32_t* f_key, const uint32_t* f_cnt, const uint32_t* block_offsets,
+                       uint32_t max_pairs, uint64_t* keys, uint32_t* vals, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((n + kProjBlock - 1) / kProjBlock);
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(kProjBlock), 0, s, n, cam, f_mx, f_my, f_a,
+                     f_b, f_c, f_tau, f_key, f_cnt, block_offsets, max_pairs, keys, vals);
+  return hipGetLastError();
+}
+
+}  // namespace higs

@@ -1,0 +1,512 @@
+// The C-ABI of libhigs: context (workspace sized up front, sec. 3.1's
+// "preallocated up front"), stage entry points, counts, debug read-back,
+// per-kernel timers.  Every stage only enqueues kernels on the caller's
+// stream; data-dependent sizes (pairs, batches) stay on the device.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "higs_internal.h"
+
+using namespace higs;
+
+struct higs_ctx {
+  int device = 0;
+  int n_cus = 0;
+  higs_params params{};
+  int64_t max_g = 0, max_pairs = 0, max_batches = 0;
+  int32_t max_w = 0, max_h = 0, max_mt = 0;
+
+  float *f_mx = nullptr, *f_my = nullptr, *f_a = nullptr, *f_b = nullptr, *f_c = nullptr,
+        *f_tau = nullptr;
+  uint32_t *f_key = nullptr, *f_cnt = nullptr;
+  RasterRecord* rec = nullptr;
+  uint32_t* block_sums = nullptr;
+  uint64_t* keys[2] = {nullptr, nullptr};
+  uint32_t* vals[2] = {nullptr, nullptr};
+  uint64_t* dbg_keys = nullptr;
+  uint32_t* dbg_vals = nullptr;
+  uint32_t* hist = nullptr;
+  uint32_t* plan = nullptr;
+  uint64_t* status = nullptr;
+  uint32_t max_tiles = 0;
+  uint32_t *mt_off = nullptr, *batch_first = nullptr, *batch_tab = nullptr, *active = nullptr;
+  float4* partials = nullptr;
+  DeviceCounters* dc = nullptr;
+
+  // frame state
+  higs_camera cam{};
+  CamArgs ca{};
+  ParamArgs pa{};
+  int64_t n = 0;
+  int stage = 0;  // 1 projected, 2 sorted, 3 batched, 4 rastered
+  int n_mt = 0, n_passes = 0;
+  uint32_t epoch = 1;
+  hipStream_t last_stream = nullptr;
+  int debug_flags = 0;
+  bool timing = false;
+  bool timers_valid = false;
+  hipEvent_t ev[HIGS_NUM_TIMERS][2] = {};
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+template <class T>
+int dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    return HIGS_E_NOMEM;
+  }
+  return HIGS_OK;
+}
+
+void free_all(higs_ctx* c) {
+  void* bufs[] = {c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau, c->f_key, c->f_cnt,
+                  c->rec, c->block_sums, c->keys[0], c->keys[1], c->vals[0], c->vals[1],
+                  c->dbg_keys, c->dbg_vals, c->hist, c->plan, c->status, c->mt_off,
+                  c->batch_first, c->batch_tab, c->active, c->partials, c->dc};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  for (int k = 0; k < HIGS_NUM_TIMERS; ++k)
+    for (int e = 0; e < 2; ++e)
+      if (c->ev[k][e]) (void)hipEventDestroy(c->ev[k][e]);
+}
+
+int n_bits(uint32_t v) {  // bits needed to hold 0..v
+  int b = 0;
+  while (v) {
+    ++b;
+    v >>= 1;
+  }
+  return b;
+}
+
+int hip_err(hipError_t e) {
+  if (e != hipSuccess) {
+    fprintf(stderr, "libhigs: HIP error %d (%s)\n", (int)e, hipGetErrorString(e));
+    return HIGS_E_HIP;
+  }
+  return HIGS_OK;
+}
+
+struct TimerScope {
+  higs_ctx* c;
+  int slot;
+  hipStream_t s;
+  TimerScope(higs_ctx* ctx, int k, hipStream_t st) : c(ctx), slot(k), s(st) {
+    if (c->timing) (void)hipEventRecord(c->ev[slot][0], s);
+  }
+  ~TimerScope() {
+    if (c->timing) (void)hipEventRecord(c->ev[slot][1], s);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+void higs_default_params(higs_params* p) {
+  if (!p) return;
+  p->tile_px = 8;
+  p->mt_tiles_x = 8;
+  p->mt_tiles_y = 4;
+  p->batch_cap = 1024;
+  p->sh_degree = 3;
+  p->alpha_max = 0.99f;
+  p->t_eps = 1e-4f;
+  p->near_z = 0.2f;
+  p->dilation = 0.3f;
+}
+
+const char* higs_error_string(int code) {
+  switch (code) {
+    case HIGS_OK: return "ok";
+    case HIGS_E_INVALID: return "invalid argument";
+    case HIGS_E_NOMEM: return "out of device memory";
+    case HIGS_E_CAPACITY: return "size exceeds the context's capacity";
+    case HIGS_E_HIP: return "HIP runtime error";
+    case HIGS_E_UNSUPPORTED: return "unsupported parameter";
+    case HIGS_E_STATE: return "stage called before the stage it depends on";
+    default: return "unknown error";
+  }
+}
+
+int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians,
+                    int64_t max_pairs, int64_t max_batches, int32_t max_width,
+                    int32_t max_height, higs_ctx** out) {
+  if (!out) return HIGS_E_INVALID;
+  *out = nullptr;
+  higs_params p;
+  if (params) p = *params;
+  else higs_default_params(&p);
+  if (p.tile_px != kTile || p.mt_tiles_x != kMtTilesX || p.mt_tiles_y != kMtTilesY)
+    return HIGS_E_UNSUPPORTED;
+  if (p.sh_degree < 0 || p.sh_degree > 3) return HIGS_E_UNSUPPORTED;
+  if (p.batch_cap < 1 || p.batch_cap > kMaxBatch) return HIGS_E_INVALID;
+  if (!(p.alpha_max > 0.0f && p.alpha_max <= 1.0f) || !(p.t_eps >= 0.0f) ||
+      !(p.dilation >= 0.0f) || !(p.near_z == p.near_z))
+    return HIGS_E_INVALID;
+  if (max_gaussians < 1 || max_pairs < 1 || max_batches < 1 || max_width < 1 || max_height < 1)
+    return HIGS_E_INVALID;
+  if (max_gaussians > (int64_t)0x7fffffff || max_pairs > (int64_t)0xfffff000 ||
+      max_batches > (int64_t)0x7fffffff)
+    return HIGS_E_INVALID;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HIGS_E_INVALID;
+  DeviceGuard g(device);
+  higs_ctx* c = new (std::nothrow) higs_ctx();
+  if (!c) return HIGS_E_NOMEM;
+  c->device = device;
+  c->params = p;
+  c->max_g = max_gaussians;
+  c->max_pairs = max_pairs;
+  c->max_batches = max_batches;
+  c->max_w = max_width;
+  c->max_h = max_height;
+  c->max_mt = ((max_width + kMtW - 1) / kMtW) * ((max_height + kMtH - 1) / kMtH);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete c;
+    return HIGS_E_HIP;
+  }
+  c->n_cus = prop.multiProcessorCount;
+  const size_t G = (size_t)max_gaussians, P = (size_t)max_pairs, B = (size_t)max_batches;
+  const size_t nblk = (G + kProjBlock - 1) / kProjBlock;
+  c->max_tiles = (uint32_t)((P + kSortTile - 1) / kSortTile);
+  int rc = HIGS_OK;
+  rc |= dalloc(&c->f_mx, G);
+  rc |= dalloc(&c->f_my, G);
+  rc |= dalloc(&c->f_a, G);
+  rc |= dalloc(&c->f_b, G);
+  rc |= dalloc(&c->f_c, G);
+  rc |= dalloc(&c->f_tau, G);
+  rc |= dalloc(&c->f_key, G);
+  rc |= dalloc(&c->f_cnt, G);
+  rc |= dalloc(&c->rec, G);
+  rc |= dalloc(&c->block_sums, 2 * nblk);
+  rc |= dalloc(&c->keys[0], P);
+  rc |= dalloc(&c->keys[1], P);
+  rc |= dalloc(&c->vals[0], P);
+  rc |= dalloc(&c->vals[1], P);
+  rc |= dalloc(&c->hist, (size_t)kMaxPasses * kRadix);
+  rc |= dalloc(&c->plan, (size_t)kMaxPasses + (size_t)kMaxPasses * kRadix);
+  rc |= dalloc(&c->status, (size_t)c->max_tiles * kRadix);
+  rc |= dalloc(&c->mt_off, (size_t)c->max_mt + 1);
+  rc |= dalloc(&c->batch_first, (size_t)c->max_mt + 1);
+  rc |= dalloc(&c->batch_tab, 3 * B);
+  rc |= dalloc(&c->active, B);
+  rc |= dalloc(&c->partials, B * kTilesPerMt * 64);
+  rc |= dalloc(&c->dc, 1);
+  if (rc != HIGS_OK) {
+    free_all(c);
+    delete c;
+    return HIGS_E_NOMEM;
+  }
+  // look-back words start untagged (epoch 0 never matches a pass)
+  if (hipMemset(c->status, 0, (size_t)c->max_tiles * kRadix * sizeof(uint64_t)) != hipSuccess ||
+      hipMemset(c->dc, 0, sizeof(DeviceCounters)) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    free_all(c);
+    delete c;
+    return HIGS_E_HIP;
+  }
+  for (int k = 0; k < HIGS_NUM_TIMERS; ++k)
+    for (int e = 0; e < 2; ++e)
+      if (hipEventCreate(&c->ev[k][e]) != hipSuccess) {
+        free_all(c);
+        delete c;
+        return HIGS_E_HIP;
+      }
+  *out = c;
+  return HIGS_OK;
+}
+
+int higs_ctx_destroy(higs_ctx* c) {
+  if (!c) return HIGS_E_INVALID;
+  DeviceGuard g(c->device);
+  (void)hipDeviceSynchronize();
+  free_all(c);
+  delete c;
+  return HIGS_OK;
+}
+
+int higs_set_debug(higs_ctx* c, int flags) {
+  if (!c) return HIGS_E_INVALID;
+  DeviceGuard g(c->device);
+  if ((flags & HIGS_DEBUG_KEEP_PAIRS) && !c->dbg_keys) {
+    if (dalloc(&c->dbg_keys, (size_t)c->max_pairs) != HIGS_OK ||
+        dalloc(&c->dbg_vals, (size_t)c->max_pairs) != HIGS_OK)
+      return HIGS_E_NOMEM;
+  }
+  c->debug_flags = flags;
+  return HIGS_OK;
+}
+
+int higs_set_timing(higs_ctx* c, int on) {
+  if (!c) return HIGS_E_INVALID;
+  c->timing = on != 0;
+  c->timers_valid = false;
+  return HIGS_OK;
+}
+
+int higs_project(higs_ctx* c, int64_t n, const float* means, const float* scales,
+                 const float* quats, const float* opacities, const float* sh,
+                 const higs_camera* cam, void* stream) {
+  if (!c || !cam || n < 0) return HIGS_E_INVALID;
+  if (n > 0 && (!means || !scales || !quats || !opacities || !sh)) return HIGS_E_INVALID;
+  if (cam->width < 1 || cam->height < 1) return HIGS_E_INVALID;
+  if (!(cam->fx > 0.0f) || !(cam->fy > 0.0f)) return HIGS_E_INVALID;
+  if (n > c->max_g || cam->width > c->max_w || cam->height > c->max_h) return HIGS_E_CAPACITY;
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  c->stage = 0;
+  c->timers_valid = c->timing;
+  c->cam = *cam;
+  c->n = n;
+  CamArgs& a = c->ca;
+  a.width = cam->width;
+  a.height = cam->height;
+  a.n_mt_x = (cam->width + kMtW - 1) / kMtW;
+  a.n_mt_y = (cam->height + kMtH - 1) / kMtH;
+  a.fx = cam->fx;
+  a.fy = cam->fy;
+  a.cx = cam->cx;
+  a.cy = cam->cy;
+  for (int r = 0; r < 3; ++r) {
+    for (int k = 0; k < 3; ++k) a.R[r * 3 + k] = cam->world_to_cam[r * 4 + k];
+    a.t[r] = cam->world_to_cam[r * 4 + 3];
+  }
+  for (int k = 0; k < 3; ++k) a.bg[k] = cam->background[k];
+  c->pa.alpha_max = c->params.alpha_max;
+  c->pa.t_eps = c->params.t_eps;
+  c->pa.near_z = c->params.near_z;
+  c->pa.dilation = c->params.dilation;
+  c->pa.batch_cap = c->params.batch_cap;
+  c->pa.sh_degree = c->params.sh_degree;
+  c->n_mt = a.n_mt_x * a.n_mt_y;
+  c->n_passes = (32 + n_bits((uint32_t)(c->n_mt - 1)) + kRadixBits - 1) / kRadixBits;
+  int rc = hip_err(launch_clear(c->dc, c->hist, kMaxPasses * kRadix, s));
+  if (rc) return rc;
+  {
+    TimerScope ts(c, HIGS_TIMER_PROJECT, s);
+    rc = hip_err(launch_project(n, means, scales, quats, opacities, sh, c->ca, c->pa, c->f_mx,
+                                c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau, c->f_key, c->f_cnt,
+                                c->rec, c->block_sums, s));
+  }
+  if (rc) return rc;
+  c->stage = 1;
+  return HIGS_OK;
+}
+
+int higs_bin_sort(higs_ctx* c, void* stream) {
+  if (!c) return HIGS_E_INVALID;
+  if (c->stage < 1) return HIGS_E_STATE;
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  int rc;
+  {
+    TimerScope ts(c, HIGS_TIMER_SCAN, s);
+    rc = hip_err(launch_scan(c->n > 0 ? c->n : 0, c->f_cnt, c->block_sums,
+                             (uint32_t)c->max_pairs, c->dc, s));
+  }
+  if (rc) return rc;
+  {
+    TimerScope ts(c, HIGS_TIMER_FILL, s);
+    rc = hip_err(launch_fill(c->n, c->ca, c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau,
+                             c->f_key, c->f_cnt, c->block_sums, (uint32_t)c->max_pairs, c->keys[0],
+                             c->vals[0], s));
+  }
+  if (rc) return rc;
+  if ((c->debug_flags & HIGS_DEBUG_KEEP_PAIRS) && c->dbg_keys) {
+    rc = hip_err(hipMemcpyAsync(c->dbg_keys, c->keys[0], (size_t)c->max_pairs * 8,
+                                hipMemcpyDeviceToDevice, s));
+    if (!rc) rc = hip_err(hipMemcpyAsync(c->dbg_vals, c->vals[0], (size_t)c->max_pairs * 4,
+                                         hipMemcpyDeviceToDevice, s));
+    if (rc) return rc;
+  }
+  SortBuffers sb;
+  sb.keys[0] = c->keys[0];
+  sb.keys[1] = c->keys[1];
+  sb.vals[0] = c->vals[0];
+  sb.vals[1] = c->vals[1];
+  sb.hist = c->hist;
+  sb.plan = c->plan;
+  sb.status = c->status;
+  sb.max_tiles = c->max_tiles;
+  {
+    TimerScope ts(c, HIGS_TIMER_SORT, s);
+    rc = hip_err(launch_sort(c->n_passes, c->epoch, sb, c->dc, c->n_cus, s));
+  }
+  c->epoch += (uint32_t)c->n_passes;
+  if (c->epoch >= (1u << 30) - 64) c->epoch = 1;  // status words hold 30 epoch bits
+  if (rc) return rc;
+  c->stage = 2;
+  return HIGS_OK;
+}
+
+int higs_batch(higs_ctx* c, void* stream) {
+  if (!c) return HIGS_E_INVALID;
+  if (c->stage < 2) return HIGS_E_STATE;
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  const uint64_t* k2[2] = {c->keys[0], c->keys[1]};
+  int rc;
+  {
+    TimerScope ts(c, HIGS_TIMER_BATCH, s);
+    rc = hip_err(launch_batch(c->n_mt, (uint32_t)c->params.batch_cap, (uint32_t)c->max_batches, k2,
+                              c->dc, c->mt_off, c->batch_first, c->batch_tab, s));
+  }
+  if (rc) return rc;
+  c->stage = 3;
+  return HIGS_OK;
+}
+
+int higs_raster(higs_ctx* c, float* image, float* T_out, void* stream) {
+  if (!c || !image) return HIGS_E_INVALID;
+  if (c->stage < 3) return HIGS_E_STATE;
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  const uint32_t* v2[2] = {c->vals[0], c->vals[1]};
+  int rc;
+  {
+    TimerScope ts(c, HIGS_TIMER_RASTER, s);
+    rc = hip_err(launch_raster(c->ca, c->pa, v2, c->rec, c->batch_tab, c->dc, c->partials,
+                               c->active, c->n_cus, s));
+  }
+  if (rc) return rc;
+  {
+    TimerScope ts(c, HIGS_TIMER_MERGE, s);
+    rc = hip_err(launch_merge(c->ca, c->pa, c->batch_first, c->active, c->partials, c->dc, image,
+                              T_out, s));
+  }
+  if (rc) return rc;
+  c->stage = 4;
+  return HIGS_OK;
+}
+
+int higs_render(higs_ctx* c, int64_t n, const float* means, const float* scales,
+                const float* quats, const float* opacities, const float* sh,
+                const higs_camera* cam, float* image, float* T_out, void* stream) {
+  if (!image) return HIGS_E_INVALID;
+  int rc = higs_project(c, n, means, scales, quats, opacities, sh, cam, stream);
+  if (rc) return rc;
+  rc = higs_bin_sort(c, stream);
+  if (rc) return rc;
+  rc = higs_batch(c, stream);
+  if (rc) return rc;
+  return higs_raster(c, image, T_out, stream);
+}
+
+int higs_get_counts(higs_ctx* c, higs_counts* out) {
+  if (!c || !out) return HIGS_E_INVALID;
+  DeviceGuard g(c->device);
+  if (hipStreamSynchronize(c->last_stream) != hipSuccess) return HIGS_E_HIP;
+  DeviceCounters h;
+  if (hipMemcpy(&h, c->dc, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return HIGS_E_HIP;
+  out->n_gaussians = c->n;
+  out->n_visible = c->stage >= 2 ? (int64_t)h.n_visible : 0;
+  out->n_pairs = c->stage >= 2 ? (int64_t)h.n_pairs_total : 0;
+  out->n_batches = c->stage >= 3 ? (int64_t)h.n_batches_total : 0;
+  out->overflow = h.overflow;
+  return HIGS_OK;
+}
+
+int higs_debug_copy(higs_ctx* c, int which, void* host_dst, size_t bytes) {
+  if (!c || !host_dst) return HIGS_E_INVALID;
+  DeviceGuard g(c->device);
+  if (hipStreamSynchronize(c->last_stream) != hipSuccess) return HIGS_E_HIP;
+  DeviceCounters h;
+  if (hipMemcpy(&h, c->dc, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return HIGS_E_HIP;
+  const size_t n = (size_t)c->n;
+  const size_t np = h.n_pairs, nb = h.n_batches;
+  char* dst = static_cast<char*>(host_dst);
+  auto cp = [&](const void* src, size_t len) {
+    return hipMemcpy(dst, src, len, hipMemcpyDeviceToHost) == hipSuccess ? HIGS_OK : HIGS_E_HIP;
+  };
+  switch (which) {
+    case HIGS_DBG_PROJ: {
+      if (c->stage < 1 || bytes > 8 * n * 4) return HIGS_E_INVALID;
+      const void* cols[8] = {c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau, c->f_key, c->f_cnt};
+      size_t left = bytes;
+      for (int k = 0; k < 8 && left > 0; ++k) {
+        const size_t len = left < n * 4 ? left : n * 4;
+        if (hipMemcpy(dst + k * n * 4, cols[k], len, hipMemcpyDeviceToHost) != hipSuccess)
+          return HIGS_E_HIP;
+        left -= len;
+      }
+      return HIGS_OK;
+    }
+    case HIGS_DBG_RECORDS:
+      if (c->stage < 1 || bytes > n * sizeof(RasterRecord)) return HIGS_E_INVALID;
+      return cp(c->rec, bytes);
+    case HIGS_DBG_PAIRS:
+    case HIGS_DBG_SORTED: {
+      if (c->stage < 2 || bytes > np * 12) return HIGS_E_INVALID;
+      const uint64_t* k;
+      const uint32_t* v;
+      if (which == HIGS_DBG_PAIRS) {
+        if (!(c->debug_flags & HIGS_DEBUG_KEEP_PAIRS) || !c->dbg_keys) return HIGS_E_STATE;
+        k = c->dbg_keys;
+        v = c->dbg_vals;
+      } else {
+        k = c->keys[h.sort_final & 1u];
+        v = c->vals[h.sort_final & 1u];
+      }
+      const size_t kb = bytes < np * 8 ? bytes : np * 8;
+      if (hipMemcpy(dst, k, kb, hipMemcpyDeviceToHost) != hipSuccess) return HIGS_E_HIP;
+      if (bytes > np * 8 &&
+          hipMemcpy(dst + np * 8, v, bytes - np * 8, hipMemcpyDeviceToHost) != hipSuccess)
+        return HIGS_E_HIP;
+      return HIGS_OK;
+    }
+    case HIGS_DBG_MT_OFFSETS:
+      if (c->stage < 3 || bytes > ((size_t)c->n_mt + 1) * 4) return HIGS_E_INVALID;
+      return cp(c->mt_off, bytes);
+    case HIGS_DBG_BATCHES:
+      if (c->stage < 3 || bytes > nb * 12) return HIGS_E_INVALID;
+      return cp(c->batch_tab, bytes);
+    case HIGS_DBG_ACTIVE:
+      if (c->stage < 4 || bytes > nb * 4) return HIGS_E_INVALID;
+      return cp(c->active, bytes);
+    case HIGS_DBG_PARTIALS:
+      if (c->stage < 4 || bytes > nb * kTilesPerMt * 64 * 16) return HIGS_E_INVALID;
+      return cp(c->partials, bytes);
+    default:
+      return HIGS_E_INVALID;
+  }
+}
+
+int higs_get_timers(higs_ctx* c, float ms[HIGS_NUM_TIMERS]) {
+  if (!c || !ms) return HIGS_E_INVALID;
+  if (!c->timing || !c->timers_valid || c->stage < 4) return HIGS_E_STATE;
+  DeviceGuard g(c->device);
+  if (hipStreamSynchronize(c->last_stream) != hipSuccess) return HIGS_E_HIP;
+  for (int k = 0; k < HIGS_NUM_TIMERS; ++k) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, c->ev[k][0], c->ev[k][1]) != hipSuccess) return HIGS_E_HIP;
+    ms[k] = t;
+  }
+  return HIGS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// Internal declarations shared by the libhigs translation units (GPU side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/higs.h"
+
+namespace higs {
+
+// Tile geometry (sec. 3.1): 8x8-pixel render tiles, 8x4 of them per
+// 64x32-pixel macro-tile.
+constexpr int kTile = 8;
+constexpr int kMtTilesX = 8;
+constexpr int kMtTilesY = 4;
+constexpr int kMtW = kTile * kMtTilesX;  // 64
+constexpr int kMtH = kTile * kMtTilesY;  // 32
+constexpr int kTilesPerMt = kMtTilesX * kMtTilesY;  // 32
+constexpr int kMaxBatch = 1024;  // largest B_r the rasteriser's LDS holds
+
+constexpr int kProjBlock = 256;  // gaussians per projection / emission block
+
+// Radix sort geometry.
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;                         // keys per thread
+constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys per tile
+constexpr int kMaxPasses = 8;
+
+// Raster record written by the projection for every visible gaussian and
+// gathered by the rasteriser: 48 bytes, three 16-byte loads.
+struct alignas(16) RasterRecord {
+  float mx, my, l0, l1;  // centre (pixels), Cholesky factors of Sigma^-1
+  float l2, o, r, g;     // ..., opacity, colour
+  float b, tau, pad0, pad1;  // ..., opacity level q <= tau
+};
+static_assert(sizeof(RasterRecord) == 48, "record layout");
+
+// Internal error bit in DeviceCounters::overflow: a sort look-back gave up
+// waiting (reported through higs_get_counts; the frame is then invalid).
+constexpr uint32_t kErrSortStall = 0x80000000u;
+
+// Frame-wide device counters; cleared by a kernel at the start of each frame.
+struct DeviceCounters {
+  uint32_t n_pairs_total;   // all pairs asked for (may exceed capacity)
+  uint32_t n_pairs;         // pairs stored = min(total, capacity)
+  uint32_t n_visible;
+  uint32_t n_batches_total;
+  uint32_t n_batches;       // = min(total, capacity)
+  uint32_t overflow;        // HIGS_OVF_* bits
+  uint32_t sort_final;      // which key/value buffer holds the sorted pairs
+  uint32_t raster_next;     // work counter of the persistent rasteriser
+  uint32_t tile_next[kMaxPasses];  // work counters of the sort passes
+  uint32_t pad[16];
+};
+
+// Camera data passed by value to kernels.
+struct CamArgs {
+  int32_t width, height;
+  int32_t n_mt_x, n_mt_y;
+  float fx, fy, cx, cy;
+  float R[9];
+  float t[3];
+  float bg[3];
+};
+
+struct ParamArgs {
+  float alpha_max, t_eps, near_z, dilation;
+  int32_t batch_cap, sh_degree;
+};
+
+// ---- host-side launchers (one translation unit each) ----------------------
+hipError_t launch_clear(DeviceCounters* dc, uint32_t* hist, int n_hist, hipStream_t s);
+
+hipError_t launch_project(int64_t n, const float* means, const float* scales, const float* quats,
+                          const float* opac, const float* sh, CamArgs cam, ParamArgs prm,
+                          float* f_mx, float* f_my, float* f_a, float* f_b, float* f_c,
+                          float* f_tau, uint32_t* f_key, uint32_t* f_cnt, RasterRecord* rec,
+                          uint32_t* block_sums, hipStream_t s);
+
+hipError_t launch_scan(int64_t n, const uint32_t* cnt, uint32_t* block_sums, uint32_t max_pairs,
+                       DeviceCounters* dc, hipStream_t s);
+
+hipError_t launch_fill(int64_t n, CamArgs cam, const float* f_mx, const float* f_my,
+                       const float* f_a, const float* f_b, const float* f_c, const float* f_tau,
+                       const uint32_t* f_key, const uint32_t* f_cnt, const uint32_t* block_offsets,
+                       uint32_t max_pairs, uint64_t* keys, uint32_t* vals, hipStream_t s);
+
+struct SortBuffers {
+  uint64_t* keys[2];
+  uint32_t* vals[2];
+  uint32_t* hist;        // [kMaxPasses][kRadix]
+  uint32_t* plan;        // [kMaxPasses] src buffer index (~0u: pass skipped), then
+                         // [kMaxPasses][kRadix] exclusive digit bases
+  uint64_t* status;      // [max_tiles][kRadix] look-back words
+  uint32_t max_tiles;
+};
+hipError_t launch_sort(int n_passes, uint32_t epoch_base, SortBuffers sb, DeviceCounters* dc,
+                       int n_cus, hipStream_t s);
+
+hipError_t launch_batch(int n_mt, uint32_t batch_cap, uint32_t max_batches, const uint64_t* const* keys2,
+                        DeviceCounters* dc, uint32_t* mt_off, uint32_t* batch_first,
+                        uint32_t* batch_tab, hipStream_t s);
+
+hipError_t launch_raster(CamArgs cam, ParamArgs prm, const uint32_t* const* vals2,
+                         const RasterRecord* rec, const uint32_t* batch_tab,
+                         DeviceCounters* dc, float4* partials, uint32_t* active, int n_cus,
+                         hipStream_t s);
+
+hipError_t launch_merge(CamArgs cam, ParamArgs prm, const uint32_t* batch_first,
+                        const uint32_t* active, const float4* partials, const DeviceCounters* dc,
+                        float* image, float* T_out, hipStream_t s);
+
+int raster_workers_per_cu();
+
+}  // namespace higs

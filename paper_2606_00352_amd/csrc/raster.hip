@@ -1,0 +1,269 @@
+// Stage 4: macro-tile rasterisation (sec. 3.4, Algorithms 1 and 2) and the
+// post-blend merge of Eq. 1.
+//
+// raster_kernel: persistent; each workgroup (8 waves) claims (macro-tile,
+// batch) processing units from a device counter.  Per unit:
+//   Phase 1 (load + inline visibility): wave w takes mini-batches k = w, w+8
+//     (64 gaussians each, one per lane), gathers each gaussian's 48-byte record
+//     by its sorted id, stores it in LDS in macro-tile-relative pixels with
+//     the Cholesky factors prescaled by sqrt(log2(e)/2) (so exp(-q/2) becomes
+//     one exp2), and tests it against the 32 render tiles with a conservative
+//     per-tile-row ellipse scan.  The per-gaussian 32-bit tile masks become
+//     per-tile 64-bit gaussian masks with 32 wave ballots (the transpose).
+//   Queue: wave 0 ORs the masks per tile and compacts the active tiles.
+//   Phase 2: waves claim tiles from the queue through an LDS counter; a wave
+//     owns one 8x8 tile, one pixel per lane, walks the set bits of the tile's
+//     masks in depth order on the scalar unit and blends front to back in
+//     float32.  A pixel stops once T < t_eps; the wave leaves the tile once
+//     every pixel has stopped.  The partial (C, T) of every active tile is
+//     streamed out with non-temporal stores; the active-tile mask goes to a
+//     per-unit word.
+// merge_kernel: one wave per render tile walks its macro-tile's batches in
+//   depth order, reads only active partials, accumulates
+//   C += T_acc C_b, T_acc *= T_b while T_acc >= t_eps and writes
+//   C + T_acc * background.
+#include "higs_internal.h"
+
+namespace higs {
+
+constexpr int kRasterThreads = 512;
+constexpr int kRasterWaves = kRasterThreads / 64;
+constexpr int kMiniBatches = kMaxBatch / 64;  // 16
+constexpr float kSqrtHalfLog2e = 0.8493218002880191f;  // sqrt(log2(e) / 2)
+constexpr float kAlphaMin = 1.0f / 255.0f;
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+struct RasterLds {
+  float4 ga[kMaxBatch];  // mx, my (macro-tile relative), l0', l1'
+  float4 gb[kMaxBatch];  // l2', o, r, g
+  float gc[kMaxBatch];   // b
+  uint64_t masks[kMiniBatches][kTilesPerMt];
+  uint32_t queue[kTilesPerMt];
+  uint32_t qcount;
+  uint32_t qnext;
+  uint32_t unit;
+};
+
+// Conservative test of one gaussian against the macro-tile's render tiles:
+// bit (r * 8 + c) is set when the ellipse {q <= tau'} (tau' slightly above
+// tau) reaches the pixel-centre rectangle of tile (c, r).  Per tile row the
+// ellipse's x-extent over the row's centre range uses the branches
+// x = (-l1 dy +- sqrt(tau' - (l2 dy)^2)) / l0 and their extremal points.
+__device__ __forceinline__ uint32_t tile_overlap(float mx, float my, float l0, float l1, float l2,
+                                                 float tau, int tiles_x, int tiles_y) {
+  const float taum = tau * 1.01f + 0.01f;
+  const float st = sqrtf(taum);
+  const float ry = st / l2;
+  const float s12 = sqrtf(l1 * l1 + l2 * l2);
+  const float dys = -l1 * st / (l2 * s12);
+  uint32_t mask = 0;
+  for (int r = 0; r < tiles_y; ++r) {
+    const float ya = (float)(r * kTile) + 0.5f - my;
+    const float yb = (float)(r * kTile) + 7.5f - my;
+    const float dlo = fmaxf(ya, -ry), dhi = fminf(yb, ry);
+    if (!(dlo <= dhi)) continue;
+    const float yp = fminf(fmaxf(dys, dlo), dhi);
+    const float ym = fminf(fmaxf(-dys, dlo), dhi);
+    const float sp = sqrtf(fmaxf(0.0f, taum - (l2 * yp) * (l2 * yp)));
+    const float sm = sqrtf(fmaxf(0.0f, taum - (l2 * ym) * (l2 * ym)));
+    const float xp = mx + (sp - l1 * yp) / l0 + 0.5f;
+    const float xm = mx - (sm + l1 * ym) / l0 - 0.5f;
+    // tile c spans pixel centres [8c + 0.5, 8c + 7.5]
+    const float flo = fminf(fmaxf(ceilf((xm - 7.5f) * 0.125f), 0.0f), 8.0f);
+    const float fhi = fminf(fmaxf(floorf((xp - 0.5f) * 0.125f), -1.0f), (float)(tiles_x - 1));
+    const int clo = (int)flo, chi = (int)fhi;
+    if (clo <= chi) mask |= ((0xffu >> (7 - (chi - clo))) << clo) << (r * 8);
+  }
+  return mask;
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__global__ void __launch_bounds__(kRasterThreads)
+raster_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ vals0,
+              const uint32_t* __restrict__ vals1, const RasterRecord* __restrict__ rec,
+              const uint32_t* __restrict__ batch_tab, DeviceCounters* __restrict__ dc,
+              float4* __restrict__ partials, uint32_t* __restrict__ active) {
+  __shared__ RasterLds L;
+  const uint32_t* __restrict__ sorted = dc->sort_final ? vals1 : vals0;
+  const uint32_t n_units = dc->n_batches;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const float eps = prm.t_eps, amax = prm.alpha_max;
+  const float pxo = (float)(lane & 7) + 0.5f, pyo = (float)(lane >> 3) + 0.5f;
+
+  for (;;) {
+    if (tid == 0) {
+      L.unit = atomicAdd(&dc->raster_next, 1u);
+      L.qnext = 0;
+    }
+    __syncthreads();
+    const uint32_t u = L.unit;
+    if (u >= n_units) break;
+    const uint32_t mt = batch_tab[3 * u + 0];
+    const uint32_t start = batch_tab[3 * u + 1];
+    const int len = (int)batch_tab[3 * u + 2];
+    const int mtx = (int)(mt % (uint32_t)cam.n_mt_x), mty = (int)(mt / (uint32_t)cam.n_mt_x);
+    const int x0 = mtx * kMtW, y0 = mty * kMtH;
+    const int tiles_x = min(kMtTilesX, (cam.width - x0 + kTile - 1) / kTile);
+    const int tiles_y = min(kMtTilesY, (cam.height - y0 + kTile - 1) / kTile);
+    const int K = (len + 63) >> 6;
+
+    // Phase 1: load + inline visibility + transpose
+    for (int k = wave; k < K; k += kRasterWaves) {
+      const int j = k * 64 + lane;
+      uint32_t tmask = 0;
+      if (j < len) {
+        const uint32_t gid = sorted[start + j];
+        const float4* rp = reinterpret_cast<const float4*>(rec + gid);
+        const float4 A = rp[0], B = rp[1], C = rp[2];
+        const float mxr = A.x - (float)x0, myr = A.y - (float)y0;
+        L.ga[j] = make_float4(mxr, myr, A.z * kSqrtHalfLog2e, A.w * kSqrtHalfLog2e);
+        L.gb[j] = make_float4(B.x * kSqrtHalfLog2e, B.y, B.z, B.w);
+        L.gc[j] = C.x;
+        tmask = tile_overlap(mxr, myr, A.z, A.w, B.x, C.y, tiles_x, tiles_y);
+      }
+      uint64_t mine = 0;
+#pragma unroll
+      for (int t = 0; t < kTilesPerMt; ++t) {
+        const uint64_t b = __ballot((tmask >> t) & 1u);
+        if (lane == t) mine = b;
+      }
+      if (lane < kTilesPerMt) L.masks[k][lane] = mine;
+    }
+    __syncthreads();
+
+    // work queue of active tiles
+    if (wave == 0) {
+      uint64_t hit = 0;
+      if (lane < kTilesPerMt)
+        for (int k = 0; k < K; ++k) hit |= L.masks[k][lane];
+      const uint64_t act = __ballot(lane < kTilesPerMt && hit != 0);
+      if (lane < kTilesPerMt && hit != 0)
+        L.queue[__popcll(act & ((1ull << lane) - 1ull))] = (uint32_t)lane;
+      if (lane == 0) {
+        L.qcount = (uint32_t)__popcll(act);
+        active[u] = (uint32_t)act;
+      }
+    }
+    __syncthreads();
+
+    // Phase 2: waves claim tiles
+    const uint32_t qcount = L.qcount;
+    for (;;) {
+      uint32_t qi = 0;
+      if (lane == 0) qi = atomicAdd(&L.qnext, 1u);
+      qi = __builtin_amdgcn_readfirstlane(qi);
+      if (qi >= qcount) break;
+      const int t = (int)L.queue[qi];
+      const float pxr = (float)((t & 7) * kTile) + pxo;
+      const float pyr = (float)((t >> 3) * kTile) + pyo;
+      float cr = 0.0f, cg = 0.0f, cb = 0.0f, T = 1.0f;
+      for (int k = 0; k < K; ++k) {
+        uint64_t m = uniform64(L.masks[k][t]);
+        while (m) {
+          const int j = __ffsll((unsigned long long)m) - 1;
+          m &= m - 1ull;
+          const int gi = k * 64 + j;
+          const float4 A = L.ga[gi];
+          const float4 B = L.gb[gi];
+          const float bb = L.gc[gi];
+          const float dx = pxr - A.x, dy = pyr - A.y;
+          const float uu = A.z * dx + A.w * dy;
+          const float vv = B.x * dy;
+          const float q = uu * uu + vv * vv;
+          const float al = fminf(amax, B.y * __builtin_amdgcn_exp2f(-q));
+          if (T >= eps && al >= kAlphaMin) {
+            const float w = al * T;
+            cr += w * B.z;
+            cg += w * B.w;
+            cb += w * bb;
+            T = T * (1.0f - al);
+          }
+        }
+        if (__ballot(T >= eps) == 0) break;
+      }
+      v4f* dst = reinterpret_cast<v4f*>(partials + (((size_t)u * kTilesPerMt + t) * 64 + lane));
+      const v4f val = {cr, cg, cb, T};
+      __builtin_nontemporal_store(val, dst);
+    }
+    __syncthreads();
+  }
+}
+
+constexpr int kMergeThreads = 256;
+__global__ void __launch_bounds__(kMergeThreads)
+merge_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ batch_first,
+             const uint32_t* __restrict__ active, const float4* __restrict__ partials,
+             const DeviceCounters* __restrict__ dc, float* __restrict__ image,
+             float* __restrict__ T_out) {
+  const int tiles_x = (cam.width + kTile - 1) / kTile;
+  const int tiles_y = (cam.height + kTile - 1) / kTile;
+  const int tile = blockIdx.x * (kMergeThreads / 64) + (threadIdx.x >> 6);
+  if (tile >= tiles_x * tiles_y) return;
+  const int lane = threadIdx.x & 63;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const uint32_t mt = (uint32_t)((ty / kMtTilesY) * cam.n_mt_x + tx / kMtTilesX);
+  const uint32_t t = (uint32_t)((ty % kMtTilesY) * kMtTilesX + tx % kMtTilesX);
+  const uint32_t nb = dc->n_batches;
+  const uint32_t b0 = min(batch_first[mt], nb), b1 = min(batch_first[mt + 1], nb);
+  const float eps = prm.t_eps;
+  float cr = 0.0f, cg = 0.0f, cb = 0.0f, T = 1.0f;
+  for (uint32_t b = b0; b < b1; ++b) {
+    if (!((active[b] >> t) & 1u)) continue;
+    const v4f p = __builtin_nontemporal_load(
+        reinterpret_cast<const v4f*>(partials + (((size_t)b * kTilesPerMt + t) * 64 + lane)));
+    if (T >= eps) {
+      cr += T * p.x;
+      cg += T * p.y;
+      cb += T * p.z;
+      T = T * p.w;
+    }
+    if (__ballot(T >= eps) == 0) break;
+  }
+  const int x = tx * kTile + (lane & 7), y = ty * kTile + (lane >> 3);
+  if (x < cam.width && y < cam.height) {
+    const size_t pix = (size_t)y * cam.width + x;
+    image[3 * pix + 0] = cr + T * cam.bg[0];
+    image[3 * pix + 1] = cg + T * cam.bg[1];
+    image[3 * pix + 2] = cb + T * cam.bg[2];
+    if (T_out) T_out[pix] = T;
+  }
+}
+
+static int g_raster_per_cu = 0;
+
+hipError_t launch_raster(CamArgs cam, ParamArgs prm, const uint32_t* const* vals2,
+                         const RasterRecord* rec, const uint32_t* batch_tab,
+                         DeviceCounters* dc, float4* partials, uint32_t* active, int n_cus,
+                         hipStream_t s) {
+  if (g_raster_per_cu == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, raster_kernel, kRasterThreads, 0) !=
+            hipSuccess ||
+        nb < 1)
+      nb = 1;
+    g_raster_per_cu = nb;
+  }
+  hipLaunchKernelGGL(raster_kernel, dim3(n_cus * g_raster_per_cu), dim3(kRasterThreads), 0, s, cam,
+                     prm, vals2[0], vals2[1], rec, batch_tab, dc, partials, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge(CamArgs cam, ParamArgs prm, const uint32_t* batch_first,
+                        const uint32_t* active, const float4* partials, const DeviceCounters* dc,
+                        float* image, float* T_out, hipStream_t s) {
+  const int tiles = ((cam.width + kTile - 1) / kTile) * ((cam.height + kTile - 1) / kTile);
+  const int blocks = (tiles + (kMergeThreads / 64) - 1) / (kMergeThreads / 64);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(merge_kernel, dim3(blocks), dim3(kMergeThreads), 0, s, cam, prm, batch_first,
+                     active, partials, dc, image, T_out);
+  return hipGetLastError();
+}
+
+int raster_workers_per_cu() { return g_raster_per_cu; }
+
+}  // namespace higs

@@ -1,0 +1,257 @@
+// Stage 2b: depth sort of the (macro-tile, gaussian) pairs (sec. 3.3: each
+// macro-tile's list ordered by depth; ties by gaussian id).
+//
+// A stable least-significant-digit radix sort over the composite 64-bit key
+// (macro-tile << 32 | float32 depth bits) with the gaussian id as value.
+// Pairs arrive in gaussian-id order and every pass is stable, so the result
+// is ordered by (macro-tile, depth, id).  One pass per 8-bit digit of the
+// 32 + ceil(log2 n_mt) significant key bits, each a single "onesweep" kernel:
+//   - a persistent grid claims 4096-key tiles from a device counter, so tile
+//     t's predecessors are always resident (forward progress of the look-back);
+//   - each wave ranks its 1024 keys stably with 8 ballots per key (wave-level
+//     multisplit) against a wave-private digit histogram in LDS;
+//   - per digit, the tile publishes its count and looks back over the
+//     preceding tiles' published counts/prefixes (decoupled look-back, one
+//     thread per digit, 64-bit status words tagged with a per-pass epoch so
+//     the status array never needs clearing);
+//   - keys are regrouped by digit in LDS and written out in runs.
+// A histogram kernel counts every digit position in one read of the keys; a
+// plan kernel turns the counts into per-pass digit bases and skips a pass
+// whose digit is the same for every key (the ping-pong buffer choice is then
+// made on the device, so no host round trip is needed).
+#include "higs_internal.h"
+
+namespace higs {
+
+__device__ __forceinline__ uint64_t ld_status(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_status(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr uint32_t kMaxSpins = 1u << 22;  // look-back bound: every wave exits
+constexpr uint32_t kFlagAggregate = 1u;
+constexpr uint32_t kFlagPrefix = 2u;
+__device__ __forceinline__ uint64_t status_word(uint32_t epoch, uint32_t flag, uint32_t count) {
+  return ((uint64_t)epoch << 34) | ((uint64_t)flag << 32) | (uint64_t)count;
+}
+
+constexpr int kHistThreads = 256;
+__global__ void __launch_bounds__(kHistThreads)
+sort_hist_kernel(const uint64_t* __restrict__ keys, const DeviceCounters* __restrict__ dc,
+                 int n_passes, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kMaxPasses * kRadix];
+  for (int k = threadIdx.x; k < n_passes * kRadix; k += kHistThreads) h[k] = 0;
+  __syncthreads();
+  const uint32_t n = dc->n_pairs;
+  for (uint32_t i = blockIdx.x * kHistThreads + threadIdx.x; i < n; i += gridDim.x * kHistThreads) {
+    const uint64_t key = keys[i];
+    for (int p = 0; p < n_passes; ++p)
+      atomicAdd(&h[p * kRadix + (uint32_t)((key >> (kRadixBits * p)) & (kRadix - 1))], 1u);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < n_passes * kRadix; k += kHistThreads)
+    if (h[k]) atomicAdd(&hist[k], h[k]);
+}
+
+// One block of 256 threads (one per digit): per pass, skip flag, source
+// buffer and the exclusive digit bases.
+__global__ void __launch_bounds__(kRadix)
+sort_plan_kernel(const uint32_t* __restrict__ hist, DeviceCounters* __restrict__ dc, int n_passes,
+                 uint32_t* __restrict__ plan, uint32_t* __restrict__ base) {
+  __shared__ uint32_t wave_tot[kRadix / 64];
+  const uint32_t n = dc->n_pairs;
+  const int d = threadIdx.x, lane = d & 63, wave = d >> 6;
+  uint32_t cur = 0;
+  for (int p = 0; p < n_passes; ++p) {
+    const uint32_t c = hist[p * kRadix + d];
+    const int trivial = __syncthreads_or(c == n);
+    // exclusive scan of the 256 digit counts
+    uint32_t v = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t o = __shfl_up(v, off, 64);
+      if (lane >= off) v += o;
+    }
+    if (lane == 63) wave_tot[wave] = v;
+    __syncthreads();
+    uint32_t b = v - c;
+    for (int w = 0; w < wave; ++w) b += wave_tot[w];
+    base[p * kRadix + d] = b;
+    if (d == 0) plan[p] = trivial ? 0xffffffffu : cur;
+    if (!trivial) cur ^= 1u;
+    __syncthreads();
+  }
+  if (d == 0) dc->sort_final = cur;
+}
+
+constexpr int kWaves = kSortThreads / 64;
+constexpr int kWaveItems = 64 * kSortItems;  // 1024 keys per wave
+
+struct SortLds {
+  uint64_t keys[kSortTile];
+  uint32_t vals[kSortTile];
+  uint32_t whist[kWaves][kRadix];  // per-wave digit counts, then wave prefixes
+  uint32_t local_start[kRadix];    // first LDS slot of each digit in the tile
+  uint32_t gbase[kRadix];          // global position of LDS slot 0 of each digit
+  uint32_t wave_tot[kWaves];
+  uint32_t tile;
+};
+
+__global__ void __launch_bounds__(kSortThreads)
+onesweep_kernel(int pass, uint32_t epoch, uint64_t* __restrict__ k0, uint32_t* __restrict__ v0,
+                uint64_t* __restrict__ k1, uint32_t* __restrict__ v1,
+                const uint32_t* __restrict__ plan, const uint32_t* __restrict__ base,
+                uint64_t* __restrict__ status, DeviceCounters* __restrict__ dc) {
+  __shared__ SortLds L;
+  const uint32_t src = plan[pass];
+  if (src == 0xffffffffu) return;  // every key has the same digit: identity pass
+  const uint64_t* __restrict__ kin = src ? k1 : k0;
+  const uint32_t* __restrict__ vin = src ? v1 : v0;
+  uint64_t* __restrict__ kout = src ? k0 : k1;
+  uint32_t* __restrict__ vout = src ? v0 : v1;
+  const uint32_t shift = (uint32_t)(kRadixBits * pass);
+  const uint32_t n = dc->n_pairs;
+  const uint32_t n_tiles = (n + kSortTile - 1) / kSortTile;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+
+  for (;;) {
+    if (tid == 0) L.tile = atomicAdd(&dc->tile_next[pass], 1u);
+    for (int k = tid; k < kWaves * kRadix; k += kSortThreads) (&L.whist[0][0])[k] = 0;
+    __syncthreads();
+    const uint32_t tile = L.tile;
+    if (tile >= n_tiles) break;
+    const uint32_t t0 = tile * kSortTile;
+    const uint32_t wbase = t0 + wave * kWaveItems;
+
+    uint64_t key[kSortItems];
+    uint32_t val[kSortItems];
+    uint32_t rank[kSortItems];
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+      const uint32_t idx = wbase + k * 64 + lane;
+      if (idx < n) {
+        key[k] = kin[idx];
+        val[k] = vin[idx];
+      } else {
+        key[k] = ~0ull;  // sorts last, never written out
+        val[k] = 0;
+      }
+    }
+    // stable wave-level ranking, item order (k, lane)
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+      const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
+      uint64_t peers = ~0ull;
+#pragma unroll
+      for (int b = 0; b < kRadixBits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+      }
+      const uint32_t before = (uint32_t)__popcll(peers & lt_mask);
+      const uint32_t prev = L.whist[wave][d];
+      rank[k] = prev + before;
+      if (before == 0) L.whist[wave][d] = prev + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+
+    // per digit: wave prefixes, tile count, publish, look back
+    {
+      const int d = tid;  // kSortThreads == kRadix
+      uint32_t tot = 0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) {
+        const uint32_t c = L.whist[w][d];
+        L.whist[w][d] = tot;
+        tot += c;
+      }
+      uint64_t* st = status + (size_t)tile * kRadix + d;
+      if (tile == 0) st_status(st, status_word(epoch, kFlagPrefix, tot));
+      else st_status(st, status_word(epoch, kFlagAggregate, tot));
+      // exclusive scan of the tile's digit counts -> LDS slots
+      uint32_t v = tot;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+      }
+      if (lane == 63) L.wave_tot[wave] = v;
+      uint32_t prefix = 0;
+      if (tile > 0) {
+        int64_t t = (int64_t)tile - 1;
+        uint32_t spins = 0;
+        while (t >= 0) {
+          const uint64_t w = ld_status(status + (size_t)t * kRadix + d);
+          const uint32_t flag = (uint32_t)(w >> 32) & 3u;
+          if ((uint32_t)(w >> 34) != epoch || flag == 0) {  // not published yet
+            if (++spins > kMaxSpins) {  // cannot happen unless a tile was lost
+              atomicOr(&dc->overflow, kErrSortStall);
+              break;
+            }
+            continue;
+          }
+          prefix += (uint32_t)w;
+          if (flag == kFlagPrefix) break;
+          --t;
+        }
+        st_status(st, status_word(epoch, kFlagPrefix, prefix + tot));
+      }
+      __syncthreads();
+      uint32_t ls = v - tot;
+      for (int w = 0; w < wave; ++w) ls += L.wave_tot[w];
+      L.local_start[d] = ls;
+      L.gbase[d] = base[pass * kRadix + d] + prefix - ls;
+    }
+    __syncthreads();
+    // regroup by digit in LDS
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+      const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
+      const uint32_t slot = L.local_start[d] + L.whist[wave][d] + rank[k];
+      L.keys[slot] = key[k];
+      L.vals[slot] = val[k];
+    }
+    __syncthreads();
+    const uint32_t valid = min((uint32_t)kSortTile, n - t0);
+    for (uint32_t j = tid; j < valid; j += kSortThreads) {
+      const uint64_t kk = L.keys[j];
+      const uint32_t d = (uint32_t)(kk >> shift) & (kRadix - 1);
+      const uint32_t dst = L.gbase[d] + j;
+      if (dst < n) {
+        kout[dst] = kk;
+        vout[dst] = L.vals[j];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+static int g_onesweep_per_cu = 0;
+
+hipError_t launch_sort(int n_passes, uint32_t epoch_base, SortBuffers sb, DeviceCounters* dc,
+                       int n_cus, hipStream_t s) {
+  if (g_onesweep_per_cu == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, onesweep_kernel, kSortThreads, 0) !=
+            hipSuccess ||
+        nb < 1)
+      nb = 1;
+    g_onesweep_per_cu = nb;
+  }
+  hipLaunchKernelGGL(sort_hist_kernel, dim3(n_cus * 4), dim3(kHistThreads), 0, s, sb.keys[0], dc,
+                     n_passes, sb.hist);
+  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(kRadix), 0, s, sb.hist, dc, n_passes, sb.plan,
+                     sb.plan + kMaxPasses);
+  const int workers = n_cus * g_onesweep_per_cu;
+  for (int p = 0; p < n_passes; ++p) {
+    hipLaunchKernelGGL(onesweep_kernel, dim3(workers), dim3(kSortThreads), 0, s, p,
+                       epoch_base + (uint32_t)p, sb.keys[0], sb.vals[0], sb.keys[1], sb.vals[1],
+                       sb.plan, sb.plan + kMaxPasses, sb.status, dc);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace higs

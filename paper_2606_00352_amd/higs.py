@@ -1,0 +1,282 @@
+"""Thin ctypes binding of libhigs (include/higs.h).
+
+Argument marshalling only: every step of the frame path runs in the HIP
+kernels of libhigs.so.  Torch supplies device memory (tensor.data_ptr()) and
+streams (torch.cuda.current_stream().cuda_stream, a hipStream_t on ROCm).
+There is no fallback: if the library is not built this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhigs.so")
+
+OK, E_INVALID, E_NOMEM, E_CAPACITY, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
+OVF_PAIRS, OVF_BATCHES = 1, 2
+DBG_PROJ, DBG_RECORDS, DBG_PAIRS, DBG_SORTED, DBG_MT_OFFSETS, DBG_BATCHES, DBG_ACTIVE, DBG_PARTIALS = range(1, 9)
+DEBUG_KEEP_PAIRS = 1
+TIMER_NAMES = ("project", "scan", "fill", "sort", "batch", "raster", "merge")
+
+# every symbol include/higs.h declares
+EXPORTS = ("higs_default_params", "higs_ctx_create", "higs_ctx_destroy", "higs_project",
+           "higs_bin_sort", "higs_batch", "higs_raster", "higs_render", "higs_get_counts",
+           "higs_set_debug", "higs_debug_copy", "higs_set_timing", "higs_get_timers",
+           "higs_error_string")
+
+
+class HigsError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {error_string(code)} ({code})")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("tile_px", ctypes.c_int32), ("mt_tiles_x", ctypes.c_int32),
+                ("mt_tiles_y", ctypes.c_int32), ("batch_cap", ctypes.c_int32),
+                ("sh_degree", ctypes.c_int32), ("alpha_max", ctypes.c_float),
+                ("t_eps", ctypes.c_float), ("near_z", ctypes.c_float),
+                ("dilation", ctypes.c_float)]
+
+
+class CameraC(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("world_to_cam", ctypes.c_float * 12), ("background", ctypes.c_float * 3)]
+
+
+class Counts(ctypes.Structure):
+    _fields_ = [("n_gaussians", ctypes.c_int64), ("n_visible", ctypes.c_int64),
+                ("n_pairs", ctypes.c_int64), ("n_batches", ctypes.c_int64),
+                ("overflow", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libhigs.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libhigs is not built ({LIB_PATH} missing): run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        sig = {
+            "higs_default_params": (None, [P]),
+            "higs_ctx_create": (ctypes.c_int, [ctypes.c_int, P, i64, i64, i64, i32, i32, P]),
+            "higs_ctx_destroy": (ctypes.c_int, [P]),
+            "higs_project": (ctypes.c_int, [P, i64, P, P, P, P, P, P, P]),
+            "higs_bin_sort": (ctypes.c_int, [P, P]),
+            "higs_batch": (ctypes.c_int, [P, P]),
+            "higs_raster": (ctypes.c_int, [P, P, P, P]),
+            "higs_render": (ctypes.c_int, [P, i64, P, P, P, P, P, P, P, P, P]),
+            "higs_get_counts": (ctypes.c_int, [P, P]),
+            "higs_set_debug": (ctypes.c_int, [P, ctypes.c_int]),
+            "higs_debug_copy": (ctypes.c_int, [P, ctypes.c_int, P, ctypes.c_size_t]),
+            "higs_set_timing": (ctypes.c_int, [P, ctypes.c_int]),
+            "higs_get_timers": (ctypes.c_int, [P, P]),
+            "higs_error_string": (ctypes.c_char_p, [ctypes.c_int]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def error_string(code: int) -> str:
+    return lib().higs_error_string(int(code)).decode()
+
+
+def _check(code: int, what: str):
+    if code != OK:
+        raise HigsError(code, what)
+
+
+def default_params(**overrides) -> Params:
+    p = Params()
+    lib().higs_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def camera_c(cam) -> CameraC:
+    """From any object with width, height, fx, fy, cx, cy, world_to_cam [3,4], background."""
+    c = CameraC()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    w = np.asarray(cam.world_to_cam, dtype=np.float32).reshape(-1)
+    for k in range(12):
+        c.world_to_cam[k] = float(w[k])
+    bg = getattr(cam, "background", (0.0, 0.0, 0.0))
+    for k in range(3):
+        c.background[k] = float(bg[k])
+    return c
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous() or t.dtype.itemsize != 4:
+        raise ValueError("expected a contiguous 4-byte CUDA/HIP tensor")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class Context:
+    """A libhigs context: device workspace sized for the given capacities."""
+
+    def __init__(self, max_gaussians: int, max_width: int, max_height: int, max_pairs: int = None,
+                 max_batches: int = None, device: int = 0, **params):
+        self.params = default_params(**params)
+        if max_pairs is None:
+            max_pairs = max(4 * max_gaussians, 1 << 16)
+        if max_batches is None:
+            n_mt = ((max_width + 63) // 64) * ((max_height + 31) // 32)
+            max_batches = max_pairs // max(1, self.params.batch_cap) + n_mt + 16
+        self.max_gaussians, self.max_pairs, self.max_batches = int(max_gaussians), int(max_pairs), int(max_batches)
+        self.max_width, self.max_height = int(max_width), int(max_height)
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(lib().higs_ctx_create(device, ctypes.byref(self.params), self.max_gaussians, self.max_pairs,
+                                     self.max_batches, self.max_width, self.max_height, ctypes.byref(h)),
+               "higs_ctx_create")
+        self._h = h
+        self.n = 0
+        self.n_mt = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().higs_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- stages ----------------------------------------------------------------
+    def project(self, means, scales, quats, opacities, sh, cam, stream=None):
+        n = int(means.shape[0])
+        self._cam = camera_c(cam)
+        self.n = n
+        self.n_mt = ((cam.width + 63) // 64) * ((cam.height + 31) // 32)
+        _check(lib().higs_project(self._h, n, _ptr(means), _ptr(scales), _ptr(quats), _ptr(opacities),
+                                  _ptr(sh), ctypes.byref(self._cam), _stream(stream)), "higs_project")
+
+    def bin_sort(self, stream=None):
+        _check(lib().higs_bin_sort(self._h, _stream(stream)), "higs_bin_sort")
+
+    def batch(self, stream=None):
+        _check(lib().higs_batch(self._h, _stream(stream)), "higs_batch")
+
+    def raster(self, image, T=None, stream=None):
+        _check(lib().higs_raster(self._h, _ptr(image), _ptr(T), _stream(stream)), "higs_raster")
+
+    def render(self, means, scales, quats, opacities, sh, cam, image, T=None, stream=None):
+        n = int(means.shape[0])
+        self._cam = camera_c(cam)
+        self.n = n
+        self.n_mt = ((cam.width + 63) // 64) * ((cam.height + 31) // 32)
+        _check(lib().higs_render(self._h, n, _ptr(means), _ptr(scales), _ptr(quats), _ptr(opacities),
+                                 _ptr(sh), ctypes.byref(self._cam), _ptr(image), _ptr(T), _stream(stream)),
+               "higs_render")
+
+    # ---- host read-back ----------------------------------------------------------
+    def counts(self) -> Counts:
+        c = Counts()
+        _check(lib().higs_get_counts(self._h, ctypes.byref(c)), "higs_get_counts")
+        return c
+
+    def set_debug(self, flags: int):
+        _check(lib().higs_set_debug(self._h, flags), "higs_set_debug")
+
+    def set_timing(self, on: bool):
+        _check(lib().higs_set_timing(self._h, 1 if on else 0), "higs_set_timing")
+
+    def timers(self) -> dict:
+        ms = (ctypes.c_float * len(TIMER_NAMES))()
+        _check(lib().higs_get_timers(self._h, ms), "higs_get_timers")
+        return dict(zip(TIMER_NAMES, list(ms)))
+
+    def _copy(self, which: int, arr: np.ndarray) -> np.ndarray:
+        if arr.nbytes:
+            _check(lib().higs_debug_copy(self._h, which, arr.ctypes.data_as(ctypes.c_void_p), arr.nbytes),
+                   "higs_debug_copy")
+        return arr
+
+    def proj_fields(self) -> dict:
+        raw = self._copy(DBG_PROJ, np.zeros((8, self.n), np.float32))
+        names = ("mx", "my", "a", "b", "c", "tau")
+        out = {k: raw[i] for i, k in enumerate(names)}
+        out["key"] = raw[6].view(np.uint32)
+        out["count"] = raw[7].view(np.uint32)
+        return out
+
+    def records(self) -> np.ndarray:
+        return self._copy(DBG_RECORDS, np.zeros((self.n, 12), np.float32))
+
+    def _pairs(self, which):
+        c = self.counts()
+        np_ = min(int(c.n_pairs), self.max_pairs)
+        raw = self._copy(which, np.zeros(np_ * 12, np.uint8))
+        keys = raw[:np_ * 8].view(np.uint64)
+        vals = raw[np_ * 8:].view(np.uint32)
+        return keys, vals
+
+    def pairs(self):
+        return self._pairs(DBG_PAIRS)
+
+    def sorted_pairs(self):
+        return self._pairs(DBG_SORTED)
+
+    def mt_offsets(self) -> np.ndarray:
+        return self._copy(DBG_MT_OFFSETS, np.zeros(self.n_mt + 1, np.uint32))
+
+    def batches(self) -> np.ndarray:
+        c = self.counts()
+        nb = min(int(c.n_batches), self.max_batches)
+        return self._copy(DBG_BATCHES, np.zeros((nb, 3), np.uint32))
+
+    def active(self) -> np.ndarray:
+        c = self.counts()
+        nb = min(int(c.n_batches), self.max_batches)
+        return self._copy(DBG_ACTIVE, np.zeros(nb, np.uint32))
+
+    def partials(self, first: int = 0, count: int = None) -> np.ndarray:
+        c = self.counts()
+        nb = min(int(c.n_batches), self.max_batches)
+        count = nb if count is None else min(count, nb)
+        if first != 0:
+            raise ValueError("partials are read from the first batch")
+        return self._copy(DBG_PARTIALS, np.zeros((count, 32, 64, 4), np.float32))
+
+
+def scene_tensors(scene, device="cuda"):
+    """Scene arrays (numpy float32) as contiguous device tensors."""
+    import torch
+    return tuple(torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in scene.arrays())
+
+
+def render(ctx: Context, tensors, cam, with_T: bool = True, stream=None):
+    """Renders one frame; returns (image [H,W,3], T [H,W] or None) device tensors."""
+    import torch
+    dev = tensors[0].device
+    image = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device=dev)
+    T = torch.empty((cam.height, cam.width), dtype=torch.float32, device=dev) if with_T else None
+    ctx.render(*tensors, cam, image, T, stream)
+    return image, T

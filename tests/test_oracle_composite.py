@@ -10,6 +10,10 @@ import pytest
 
 from paper_2606_00352_amd import scenes
 
+# the library interface carries these parameters as float32
+F32_DIL = float(np.float32(0.3))
+F32_AMAX = float(np.float32(0.99))
+
 
 def _iso(means, s, opac, dc, bg=(0.0, 0.0, 0.0)):
     n = len(means)
@@ -21,9 +25,9 @@ def _iso(means, s, opac, dc, bg=(0.0, 0.0, 0.0)):
 
 
 def _closed_alpha(mx, my, z, s, o, x, y, f=64.0):
-    a = (f * float(np.float32(s)) / z) ** 2 + 0.3
+    a = (f * float(np.float32(s)) / z) ** 2 + F32_DIL
     q = ((x + 0.5 - mx) ** 2 + (y + 0.5 - my) ** 2) / a
-    al = min(0.99, float(np.float32(o)) * math.exp(-q / 2))
+    al = min(F32_AMAX, float(np.float32(o)) * math.exp(-q / 2))
     return al if al >= 1 / 255 else 0.0
 
 
@@ -135,7 +139,7 @@ def test_transmittance_invariants(orc):
     for (x, y) in pix:
         d = np.stack([x + 0.5 - g[:, orc.G_MX], y + 0.5 - g[:, orc.G_MY]], -1)
         q = np.einsum("ni,nij,nj->n", d, Sinv, d)
-        al = np.minimum(0.99, g[:, orc.G_OP] * np.exp(-q / 2))
+        al = np.minimum(F32_AMAX, g[:, orc.G_OP] * np.exp(-q / 2))
         al = al[al >= 1 / 255]
         assert T[y, x] == pytest.approx(np.prod(1 - al), rel=1e-9)
         assert T[y, x] >= 0.01 ** al.size

@@ -10,6 +10,10 @@ from scipy.spatial.transform import Rotation
 
 from paper_2606_00352_amd import scenes
 
+# the library interface carries these parameters as float32
+F32_DIL = float(np.float32(0.3))
+F32_AMAX = float(np.float32(0.99))
+
 
 def _scene(means, scales, quats, opac, sh=None):
     n = len(means)
@@ -27,7 +31,7 @@ def test_isotropic_on_axis_closed_form(orc):
     valid, geo = orc.project(sc, cam)
     assert valid[0] == 1
     g = geo[0]
-    a_expect = (256.0 * float(np.float32(s)) / z) ** 2 + 0.3
+    a_expect = (256.0 * float(np.float32(s)) / z) ** 2 + F32_DIL
     assert g[orc.G_MX] == 128.0 and g[orc.G_MY] == 128.0
     assert g[orc.G_A] == pytest.approx(a_expect, rel=1e-14)
     assert g[orc.G_C] == pytest.approx(a_expect, rel=1e-14)
@@ -103,7 +107,7 @@ def test_ewa_covariance_against_numerical_jacobian(orc):
             e = np.zeros(3)
             e[k] = hstep
             J[:, k] = (_pinhole(cam, means32[i] + e)[0] - _pinhole(cam, means32[i] - e)[0]) / (2 * hstep)
-        s2 = J @ s3 @ J.T + 0.3 * np.eye(2)
+        s2 = J @ s3 @ J.T + F32_DIL * np.eye(2)
         got = np.array([[geo[i, orc.G_A], geo[i, orc.G_B]], [geo[i, orc.G_B], geo[i, orc.G_C]]])
         np.testing.assert_allclose(got, s2, rtol=1e-6, atol=1e-8 * np.abs(s2).max())
 

@@ -9,6 +9,10 @@ import scipy.special as sp
 
 from paper_2606_00352_amd import scenes
 
+# the library interface carries these parameters as float32
+F32_DIL = float(np.float32(0.3))
+F32_AMAX = float(np.float32(0.99))
+
 
 def _real_sh_scipy(l, m, d):
     """Real SH with the Condon-Shortley phase kept (3DGS checkpoint
