@@ -1,0 +1,180 @@
+"""Frame-rate benchmark of the HiGS forward path on one MI355X.
+
+Workload: 5.8M clustered gaussians (degree-3 SH), 1920x1080, the 60-view
+orbit (one step = one full frame of the path: projection, pair emission,
+depth sort, batch split, rasterisation, merge).  Inputs are synthetic, seeded,
+and resident in HBM before the timed region.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # lane-instructions/s: 256 CUs x 4 SIMD16 x 2.4 GHz
+
+# Algorithmic bytes per unit (what each kernel must move):
+#   project: reads means+scales+quats+opacity 44 B per gaussian and 192 B of SH
+#            per visible gaussian; writes depth key + count 8 B per gaussian and
+#            binning fields 24 B + raster record 48 B per visible gaussian.
+#   sort:    histogram read 8 B per pair, then per executed pass 12 B read +
+#            12 B written per pair.
+PROJECT_B_PER_GAUSSIAN = 44 + 8
+PROJECT_B_PER_VISIBLE = 192 + 24 + 48
+# Arithmetic operations per pixel-gaussian evaluation of the raster inner loop
+# (dx, dy, two for u, v, two for q, exp2, opacity product, clamp, threshold
+# test, weight, three colour FMAs, transmittance update).
+RASTER_OPS_PER_EVAL = 16
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(scene, cam, row_stride=2):
+    """The oracle (double precision, all host threads) on one view: projection,
+    binning, sort and batches over every gaussian, compositing on every
+    row_stride-th pixel row; the frame time is extrapolated to all rows."""
+    import numpy as np
+    import oracle
+    oracle.build()
+    t0 = time.perf_counter()
+    fr = oracle.frame(scene, cam, render=False)
+    t1 = time.perf_counter()
+    ys = np.arange(0, cam.height, row_stride)
+    xs = np.arange(cam.width)
+    pix = np.stack(np.meshgrid(xs, ys), -1).reshape(-1, 2)
+    oracle.render_tiled(fr.geo, fr.sorted_gid, fr.mt_off, fr.batch_tab, cam, pixels=pix)
+    t2 = time.perf_counter()
+    frame_s = (t1 - t0) + (t2 - t1) * (cam.height / len(ys))
+    return {"value": round(1.0 / frame_s, 6), "unit": "FPS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"1 view of the same workload: projection/binning/sort/batches of all "
+                      f"{scene.n} gaussians ({t1 - t0:.1f} s) + compositing of every {row_stride}th "
+                      f"pixel row ({len(pix)} px, {t2 - t1:.1f} s), frame time extrapolated to all rows"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=120)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--gaussians", type=int, default=5_800_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: the frame path is single-GPU; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2606_00352_amd import higs, scenes
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t = time.perf_counter()
+    scene, cams = scenes.config1(args.gaussians)
+    log(f"scene: {scene.n} gaussians generated in {time.perf_counter() - t:.1f} s")
+    tens = higs.scene_tensors(scene, "cuda:0")
+    torch.cuda.synchronize()
+
+    # size the context from a first frame of every view (grow on overflow)
+    max_pairs = 3 * scene.n
+    while True:
+        ctx = higs.Context(scene.n, 1920, 1080, max_pairs=max_pairs)
+        image = torch.empty((1080, 1920, 3), dtype=torch.float32, device="cuda:0")
+        worst = 0
+        ok = True
+        for cam in cams:
+            ctx.render(*tens, cam, image)
+            c = ctx.counts()
+            worst = max(worst, int(c.n_pairs))
+            if c.overflow:
+                ok = False
+        if ok:
+            break
+        max_pairs = int(worst * 1.1) + 4096
+        ctx.close()
+        log(f"growing the context to {max_pairs} pairs")
+    log(f"context: {ctx.max_pairs} pairs, {ctx.max_batches} batches")
+
+    stream = torch.cuda.current_stream()
+    for i in range(args.warmup):
+        ctx.render(*tens, cams[i % len(cams)], image)
+    torch.cuda.synchronize()
+    ctx.set_timing(min(args.steps, 1024))
+    log(f"timing {args.steps} frames")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ctx.render(*tens, cams[i % len(cams)], image)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    timers = ctx.timers()
+    ctx.set_timing(0)
+    log("kernel ms: " + ", ".join(f"{k} {v:.4f}" for k, v in timers.items()))
+
+    # sizes per view (outside the timed region), evaluation count by the
+    # rasteriser's own counter
+    ctx.set_debug(higs.DEBUG_COUNT_EVALS)
+    sizes = {"visible": [], "pairs": [], "batches": [], "passes": [], "evals": []}
+    for cam in cams:
+        ctx.render(*tens, cam, image)
+        c = ctx.counts()
+        sizes["visible"].append(c.n_visible)
+        sizes["pairs"].append(c.n_pairs)
+        sizes["batches"].append(c.n_batches)
+        sizes["passes"].append(c.sort_passes)
+        sizes["evals"].append(c.n_evaluations)
+    ctx.set_debug(0)
+    mean = {k: float(np.mean(v)) for k, v in sizes.items()}
+    n = scene.n
+    rl = {}
+    proj_bytes = PROJECT_B_PER_GAUSSIAN * n + PROJECT_B_PER_VISIBLE * mean["visible"]
+    rl["project"] = ("hbm", proj_bytes / (timers["project"] * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", proj_bytes)
+    sort_bytes = mean["pairs"] * (8 + 24 * mean["passes"])
+    rl["sort"] = ("hbm", sort_bytes / (timers["sort"] * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", sort_bytes)
+    ops = mean["evals"] * RASTER_OPS_PER_EVAL
+    rl["raster"] = ("alu", ops / (timers["raster"] * 1e-3) / 1e12, VALU_PEAK_TOPS, "Tops/s", ops)
+    dom = max(("project", "sort", "raster"), key=lambda k: timers[k])
+    bound, ach, peak, unit, work = rl[dom]
+    for k, (b, a, p, u, w) in rl.items():
+        log(f"{k}: {a:.1f} {u} of {p:.1f} ({100 * a / p:.1f}%)")
+    result = {
+        "metric": "FPS @1080p, 5.8M gaussians",
+        "value": round(1000.0 / ms_per_step, 2),
+        "unit": "FPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "5.8M clustered gaussians (SH degree 3), 1920x1080, 60-view orbit, f=1100",
+                   "gaussians": n, "width": 1920, "height": 1080, "views": len(cams),
+                   "mean_visible": round(mean["visible"]), "mean_pairs": round(mean["pairs"]),
+                   "mean_batches": round(mean["batches"]), "mean_sort_passes": mean["passes"],
+                   "kernel_ms": {k: round(v, 4) for k, v in timers.items()},
+                   "sort_pairs_per_s": round(mean["pairs"] / (timers["sort"] * 1e-3))},
+        "roofline": {"kernel": dom, "bound": bound, "achieved": round(ach, 2), "peak": round(peak, 2),
+                     "unit": unit, "frac": round(ach / peak, 4), "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        result["cpu_baseline"] = cpu_baseline(scene, cams[0])
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

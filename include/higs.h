@@ -96,6 +96,11 @@ typedef struct {
   int64_t n_pairs;     /* (macro-tile, gaussian) pairs emitted */
   int64_t n_batches;   /* (macro-tile, batch) processing units */
   uint32_t overflow;   /* HIGS_OVF_* bits */
+  int32_t sort_passes; /* radix passes that moved data (a pass whose digit is
+                          the same for every key is skipped) */
+  int64_t n_evaluations; /* pixel-gaussian evaluations of the rasteriser
+                            (64 per gaussian per render tile visited), or -1
+                            unless HIGS_DEBUG_COUNT_EVALS is set */
 } higs_counts;
 
 /* Writes the paper's defaults into *p. */
@@ -166,10 +171,13 @@ int higs_get_counts(higs_ctx* ctx, higs_counts* out);
                                where the active bit is set; pixel p of tile t sits at
                                (t % 8 * 8 + p % 8, t / 8 * 8 + p / 8) in the macro-tile */
 
-/* Debug options: HIGS_DEBUG_KEEP_PAIRS keeps a copy of the emitted pairs
+/* Debug options (bit flags): HIGS_DEBUG_KEEP_PAIRS keeps a copy of the emitted pairs
  * before the sort (allocates max_pairs * 12 bytes on first use) so that
  * HIGS_DBG_PAIRS can read them back. */
 #define HIGS_DEBUG_KEEP_PAIRS 1
+/* HIGS_DEBUG_COUNT_EVALS makes the rasteriser count its evaluations
+ * (reported in higs_counts.n_evaluations; adds one atomic per tile). */
+#define HIGS_DEBUG_COUNT_EVALS 2
 int higs_set_debug(higs_ctx* ctx, int flags);
 
 /* Copies `bytes` bytes of buffer `which` (HIGS_DBG_*) into HOST memory
@@ -177,9 +185,11 @@ int higs_set_debug(higs_ctx* ctx, int flags);
  * buffer's current content. */
 int higs_debug_copy(higs_ctx* ctx, int which, void* host_dst, size_t bytes);
 
-/* Per-kernel device times of the last frame, measured with HIP events
- * recorded on the frame's stream around each kernel group when timing is on
- * (off by default).  ms[HIGS_TIMER_*] in milliseconds; synchronises. */
+/* Per-kernel device times, measured with HIP events recorded on the frame's
+ * stream around each kernel group.  higs_set_timing(ctx, n) keeps the events
+ * of the last n frames (1..1024; 0 turns timing off, the default) without
+ * any host synchronisation; higs_get_timers synchronises and writes the mean
+ * over those frames, ms[HIGS_TIMER_*] in milliseconds. */
 #define HIGS_TIMER_PROJECT 0 /* projection + SH + per-gaussian pair counts */
 #define HIGS_TIMER_SCAN 1    /* exclusive scan of the pair counts */
 #define HIGS_TIMER_FILL 2    /* pair emission */
@@ -188,7 +198,7 @@ int higs_debug_copy(higs_ctx* ctx, int which, void* host_dst, size_t bytes);
 #define HIGS_TIMER_RASTER 5  /* per-unit rasteriser */
 #define HIGS_TIMER_MERGE 6   /* post-blend merge */
 #define HIGS_NUM_TIMERS 7
-int higs_set_timing(higs_ctx* ctx, int on);
+int higs_set_timing(higs_ctx* ctx, int n_frames);
 int higs_get_timers(higs_ctx* ctx, float ms[HIGS_NUM_TIMERS]);
 
 /* Static text for a return code. */

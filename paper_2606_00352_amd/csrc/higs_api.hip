@@ -46,9 +46,14 @@ struct higs_ctx {
   uint32_t epoch = 1;
   hipStream_t last_stream = nullptr;
   int debug_flags = 0;
-  bool timing = false;
-  bool timers_valid = false;
-  hipEvent_t ev[HIGS_NUM_TIMERS][2] = {};
+  // timing: events of the last `ring` frames, frame f in slot f % ring
+  int ring = 0;
+  int64_t frames = 0;  // frames recorded since timing was set
+  hipEvent_t* ev = nullptr;  // [ring][HIGS_NUM_TIMERS][2]
+  bool timing() const { return ring > 0; }
+  hipEvent_t event(int slot, int which) const {
+    return ev[(((frames - 1) % ring) * HIGS_NUM_TIMERS + slot) * 2 + which];
+  }
 };
 
 namespace {
@@ -76,6 +81,17 @@ int dalloc(T** p, size_t count) {
   return HIGS_OK;
 }
 
+void free_events(higs_ctx* c) {
+  if (c->ev) {
+    for (int k = 0; k < c->ring * HIGS_NUM_TIMERS * 2; ++k)
+      if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+    delete[] c->ev;
+  }
+  c->ev = nullptr;
+  c->ring = 0;
+  c->frames = 0;
+}
+
 void free_all(higs_ctx* c) {
   void* bufs[] = {c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau, c->f_key, c->f_cnt,
                   c->rec, c->block_sums, c->keys[0], c->keys[1], c->vals[0], c->vals[1],
@@ -83,9 +99,7 @@ void free_all(higs_ctx* c) {
                   c->batch_first, c->batch_tab, c->active, c->partials, c->dc};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
-  for (int k = 0; k < HIGS_NUM_TIMERS; ++k)
-    for (int e = 0; e < 2; ++e)
-      if (c->ev[k][e]) (void)hipEventDestroy(c->ev[k][e]);
+  free_events(c);
 }
 
 int n_bits(uint32_t v) {  // bits needed to hold 0..v
@@ -110,10 +124,10 @@ struct TimerScope {
   int slot;
   hipStream_t s;
   TimerScope(higs_ctx* ctx, int k, hipStream_t st) : c(ctx), slot(k), s(st) {
-    if (c->timing) (void)hipEventRecord(c->ev[slot][0], s);
+    if (c->timing()) (void)hipEventRecord(c->event(slot, 0), s);
   }
   ~TimerScope() {
-    if (c->timing) (void)hipEventRecord(c->ev[slot][1], s);
+    if (c->timing()) (void)hipEventRecord(c->event(slot, 1), s);
   }
 };
 
@@ -226,13 +240,6 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
     delete c;
     return HIGS_E_HIP;
   }
-  for (int k = 0; k < HIGS_NUM_TIMERS; ++k)
-    for (int e = 0; e < 2; ++e)
-      if (hipEventCreate(&c->ev[k][e]) != hipSuccess) {
-        free_all(c);
-        delete c;
-        return HIGS_E_HIP;
-      }
   *out = c;
   return HIGS_OK;
 }
@@ -258,10 +265,22 @@ int higs_set_debug(higs_ctx* c, int flags) {
   return HIGS_OK;
 }
 
-int higs_set_timing(higs_ctx* c, int on) {
-  if (!c) return HIGS_E_INVALID;
-  c->timing = on != 0;
-  c->timers_valid = false;
+int higs_set_timing(higs_ctx* c, int n_frames) {
+  if (!c || n_frames < 0 || n_frames > 1024) return HIGS_E_INVALID;
+  DeviceGuard g(c->device);
+  if (c->ring) (void)hipStreamSynchronize(c->last_stream);
+  free_events(c);
+  if (n_frames == 0) return HIGS_OK;
+  const int total = n_frames * HIGS_NUM_TIMERS * 2;
+  c->ev = new (std::nothrow) hipEvent_t[total];
+  if (!c->ev) return HIGS_E_NOMEM;
+  for (int k = 0; k < total; ++k) c->ev[k] = nullptr;
+  c->ring = n_frames;
+  for (int k = 0; k < total; ++k)
+    if (hipEventCreate(&c->ev[k]) != hipSuccess) {
+      free_events(c);
+      return HIGS_E_HIP;
+    }
   return HIGS_OK;
 }
 
@@ -277,7 +296,7 @@ int higs_project(higs_ctx* c, int64_t n, const float* means, const float* scales
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
   c->stage = 0;
-  c->timers_valid = c->timing;
+  if (c->timing()) c->frames += 1;
   c->cam = *cam;
   c->n = n;
   CamArgs& a = c->ca;
@@ -391,7 +410,7 @@ int higs_raster(higs_ctx* c, float* image, float* T_out, void* stream) {
   {
     TimerScope ts(c, HIGS_TIMER_RASTER, s);
     rc = hip_err(launch_raster(c->ca, c->pa, v2, c->rec, c->batch_tab, c->dc, c->partials,
-                               c->active, c->n_cus, s));
+                               c->active, c->n_cus, (c->debug_flags & HIGS_DEBUG_COUNT_EVALS) != 0, s));
   }
   if (rc) return rc;
   {
@@ -428,6 +447,10 @@ int higs_get_counts(higs_ctx* c, higs_counts* out) {
   out->n_pairs = c->stage >= 2 ? (int64_t)h.n_pairs_total : 0;
   out->n_batches = c->stage >= 3 ? (int64_t)h.n_batches_total : 0;
   out->overflow = h.overflow;
+  out->sort_passes = c->stage >= 2 ? (int32_t)h.sort_passes : 0;
+  out->n_evaluations = (c->stage >= 4 && (c->debug_flags & HIGS_DEBUG_COUNT_EVALS))
+                           ? (int64_t)h.n_evals * 64
+                           : -1;
   return HIGS_OK;
 }
 
@@ -498,13 +521,20 @@ int higs_debug_copy(higs_ctx* c, int which, void* host_dst, size_t bytes) {
 
 int higs_get_timers(higs_ctx* c, float ms[HIGS_NUM_TIMERS]) {
   if (!c || !ms) return HIGS_E_INVALID;
-  if (!c->timing || !c->timers_valid || c->stage < 4) return HIGS_E_STATE;
+  if (!c->timing() || c->frames < 1 || c->stage < 4) return HIGS_E_STATE;
   DeviceGuard g(c->device);
   if (hipStreamSynchronize(c->last_stream) != hipSuccess) return HIGS_E_HIP;
+  // frames recorded in the ring: the last min(frames, ring), all complete
+  const int64_t have = c->frames < c->ring ? c->frames : c->ring;
   for (int k = 0; k < HIGS_NUM_TIMERS; ++k) {
-    float t = 0.0f;
-    if (hipEventElapsedTime(&t, c->ev[k][0], c->ev[k][1]) != hipSuccess) return HIGS_E_HIP;
-    ms[k] = t;
+    double sum = 0.0;
+    for (int64_t f = 0; f < have; ++f) {
+      float t = 0.0f;
+      const hipEvent_t* e = c->ev + (f * HIGS_NUM_TIMERS + k) * 2;
+      if (hipEventElapsedTime(&t, e[0], e[1]) != hipSuccess) return HIGS_E_HIP;
+      sum += t;
+    }
+    ms[k] = (float)(sum / (double)have);
   }
   return HIGS_OK;
 }

@@ -52,7 +52,10 @@ struct DeviceCounters {
   uint32_t sort_final;      // which key/value buffer holds the sorted pairs
   uint32_t raster_next;     // work counter of the persistent rasteriser
   uint32_t tile_next[kMaxPasses];  // work counters of the sort passes
-  uint32_t pad[16];
+  uint32_t sort_passes;     // radix passes that moved data (others skipped)
+  uint32_t pad0;
+  unsigned long long n_evals;  // gaussian-tile evaluations (when counted)
+  uint32_t pad[12];
 };
 
 // Camera data passed by value to kernels.
@@ -106,7 +109,7 @@ hipError_t launch_batch(int n_mt, uint32_t batch_cap, uint32_t max_batches, cons
 hipError_t launch_raster(CamArgs cam, ParamArgs prm, const uint32_t* const* vals2,
                          const RasterRecord* rec, const uint32_t* batch_tab,
                          DeviceCounters* dc, float4* partials, uint32_t* active, int n_cus,
-                         hipStream_t s);
+                         bool count_evals, hipStream_t s);
 
 hipError_t launch_merge(CamArgs cam, ParamArgs prm, const uint32_t* batch_first,
                         const uint32_t* active, const float4* partials, const DeviceCounters* dc,

@@ -83,6 +83,7 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+template <bool kCountEvals>
 __global__ void __launch_bounds__(kRasterThreads)
 raster_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ vals0,
               const uint32_t* __restrict__ vals1, const RasterRecord* __restrict__ rec,
@@ -162,8 +163,10 @@ raster_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ vals0,
       const float pxr = (float)((t & 7) * kTile) + pxo;
       const float pyr = (float)((t >> 3) * kTile) + pyo;
       float cr = 0.0f, cg = 0.0f, cb = 0.0f, T = 1.0f;
+      uint32_t evals = 0;
       for (int k = 0; k < K; ++k) {
         uint64_t m = uniform64(L.masks[k][t]);
+        if (kCountEvals) evals += (uint32_t)__popcll(m);
         while (m) {
           const int j = __ffsll((unsigned long long)m) - 1;
           m &= m - 1ull;
@@ -186,6 +189,7 @@ raster_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ vals0,
         }
         if (__ballot(T >= eps) == 0) break;
       }
+      if (kCountEvals && lane == 0) atomicAdd(&dc->n_evals, (unsigned long long)evals);
       v4f* dst = reinterpret_cast<v4f*>(partials + (((size_t)u * kTilesPerMt + t) * 64 + lane));
       const v4f val = {cr, cg, cb, T};
       __builtin_nontemporal_store(val, dst);
@@ -239,17 +243,21 @@ static int g_raster_per_cu = 0;
 hipError_t launch_raster(CamArgs cam, ParamArgs prm, const uint32_t* const* vals2,
                          const RasterRecord* rec, const uint32_t* batch_tab,
                          DeviceCounters* dc, float4* partials, uint32_t* active, int n_cus,
-                         hipStream_t s) {
+                         bool count_evals, hipStream_t s) {
   if (g_raster_per_cu == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, raster_kernel, kRasterThreads, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, raster_kernel<false>, kRasterThreads, 0) !=
             hipSuccess ||
         nb < 1)
       nb = 1;
     g_raster_per_cu = nb;
   }
-  hipLaunchKernelGGL(raster_kernel, dim3(n_cus * g_raster_per_cu), dim3(kRasterThreads), 0, s, cam,
-                     prm, vals2[0], vals2[1], rec, batch_tab, dc, partials, active);
+  if (count_evals)
+    hipLaunchKernelGGL(raster_kernel<true>, dim3(n_cus * g_raster_per_cu), dim3(kRasterThreads), 0, s,
+                       cam, prm, vals2[0], vals2[1], rec, batch_tab, dc, partials, active);
+  else
+    hipLaunchKernelGGL(raster_kernel<false>, dim3(n_cus * g_raster_per_cu), dim3(kRasterThreads), 0,
+                       s, cam, prm, vals2[0], vals2[1], rec, batch_tab, dc, partials, active);
   return hipGetLastError();
 }
 

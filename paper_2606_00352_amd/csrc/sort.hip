@@ -63,7 +63,7 @@ sort_plan_kernel(const uint32_t* __restrict__ hist, DeviceCounters* __restrict__
   __shared__ uint32_t wave_tot[kRadix / 64];
   const uint32_t n = dc->n_pairs;
   const int d = threadIdx.x, lane = d & 63, wave = d >> 6;
-  uint32_t cur = 0;
+  uint32_t cur = 0, moved = 0;
   for (int p = 0; p < n_passes; ++p) {
     const uint32_t c = hist[p * kRadix + d];
     const int trivial = __syncthreads_or(c == n);
@@ -80,10 +80,16 @@ sort_plan_kernel(const uint32_t* __restrict__ hist, DeviceCounters* __restrict__
     for (int w = 0; w < wave; ++w) b += wave_tot[w];
     base[p * kRadix + d] = b;
     if (d == 0) plan[p] = trivial ? 0xffffffffu : cur;
-    if (!trivial) cur ^= 1u;
+    if (!trivial) {
+      cur ^= 1u;
+      ++moved;
+    }
     __syncthreads();
   }
-  if (d == 0) dc->sort_final = cur;
+  if (d == 0) {
+    dc->sort_final = cur;
+    dc->sort_passes = moved;
+  }
 }
 
 constexpr int kWaves = kSortThreads / 64;

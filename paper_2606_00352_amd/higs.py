@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhigs.so")
 OK, E_INVALID, E_NOMEM, E_CAPACITY, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
 OVF_PAIRS, OVF_BATCHES = 1, 2
 DBG_PROJ, DBG_RECORDS, DBG_PAIRS, DBG_SORTED, DBG_MT_OFFSETS, DBG_BATCHES, DBG_ACTIVE, DBG_PARTIALS = range(1, 9)
-DEBUG_KEEP_PAIRS = 1
+DEBUG_KEEP_PAIRS, DEBUG_COUNT_EVALS = 1, 2
 TIMER_NAMES = ("project", "scan", "fill", "sort", "batch", "raster", "merge")
 
 # every symbol include/higs.h declares
@@ -52,7 +52,8 @@ class CameraC(ctypes.Structure):
 class Counts(ctypes.Structure):
     _fields_ = [("n_gaussians", ctypes.c_int64), ("n_visible", ctypes.c_int64),
                 ("n_pairs", ctypes.c_int64), ("n_batches", ctypes.c_int64),
-                ("overflow", ctypes.c_uint32)]
+                ("overflow", ctypes.c_uint32), ("sort_passes", ctypes.c_int32),
+                ("n_evaluations", ctypes.c_int64)]
 
 
 _lib = None
@@ -205,10 +206,12 @@ class Context:
     def set_debug(self, flags: int):
         _check(lib().higs_set_debug(self._h, flags), "higs_set_debug")
 
-    def set_timing(self, on: bool):
-        _check(lib().higs_set_timing(self._h, 1 if on else 0), "higs_set_timing")
+    def set_timing(self, n_frames: int):
+        """Keep per-kernel HIP-event times of the last n_frames frames (0: off)."""
+        _check(lib().higs_set_timing(self._h, int(n_frames)), "higs_set_timing")
 
     def timers(self) -> dict:
+        """Mean per-kernel milliseconds over the recorded frames (synchronises)."""
         ms = (ctypes.c_float * len(TIMER_NAMES))()
         _check(lib().higs_get_timers(self._h, ms), "higs_get_timers")
         return dict(zip(TIMER_NAMES, list(ms)))
