@@ -191,7 +191,7 @@ int higs_debug_copy(higs_ctx* ctx, int which, void* host_dst, size_t bytes);
  * any host synchronisation; higs_get_timers synchronises and writes the mean
  * over those frames, ms[HIGS_TIMER_*] in milliseconds. */
 #define HIGS_TIMER_PROJECT 0 /* projection + SH + per-gaussian pair counts */
-#define HIGS_TIMER_SCAN 1    /* exclusive scan of the pair counts */
+#define HIGS_TIMER_SCAN 1    /* the scan runs inside the fill: this slot reads ~0 */
 #define HIGS_TIMER_FILL 2    /* pair emission */
 #define HIGS_TIMER_SORT 3    /* all radix-sort kernels */
 #define HIGS_TIMER_BATCH 4   /* macro-tile offsets + batch table */

@@ -23,7 +23,7 @@ struct higs_ctx {
         *f_tau = nullptr;
   uint32_t *f_key = nullptr, *f_cnt = nullptr;
   RasterRecord* rec = nullptr;
-  uint32_t* block_sums = nullptr;
+  uint64_t* scan_status = nullptr;  // emission look-back words, per block
   uint64_t* keys[2] = {nullptr, nullptr};
   uint32_t* vals[2] = {nullptr, nullptr};
   uint64_t* dbg_keys = nullptr;
@@ -43,7 +43,8 @@ struct higs_ctx {
   int64_t n = 0;
   int stage = 0;  // 1 projected, 2 sorted, 3 batched, 4 rastered
   int n_mt = 0, n_passes = 0;
-  uint32_t epoch = 1;
+  uint32_t epoch = 1;       // sort look-back epochs
+  uint32_t scan_epoch = 1;  // emission look-back epoch
   hipStream_t last_stream = nullptr;
   int debug_flags = 0;
   // timing: events of the last `ring` frames, frame f in slot f % ring
@@ -94,7 +95,7 @@ void free_events(higs_ctx* c) {
 
 void free_all(higs_ctx* c) {
   void* bufs[] = {c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau, c->f_key, c->f_cnt,
-                  c->rec, c->block_sums, c->keys[0], c->keys[1], c->vals[0], c->vals[1],
+                  c->rec, c->scan_status, c->keys[0], c->keys[1], c->vals[0], c->vals[1],
                   c->dbg_keys, c->dbg_vals, c->hist, c->plan, c->status, c->mt_off,
                   c->batch_first, c->batch_tab, c->active, c->partials, c->dc};
   for (void* b : bufs)
@@ -213,7 +214,7 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
   rc |= dalloc(&c->f_key, G);
   rc |= dalloc(&c->f_cnt, G);
   rc |= dalloc(&c->rec, G);
-  rc |= dalloc(&c->block_sums, 2 * nblk);
+  rc |= dalloc(&c->scan_status, nblk);
   rc |= dalloc(&c->keys[0], P);
   rc |= dalloc(&c->keys[1], P);
   rc |= dalloc(&c->vals[0], P);
@@ -234,6 +235,7 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
   }
   // look-back words start untagged (epoch 0 never matches a pass)
   if (hipMemset(c->status, 0, (size_t)c->max_tiles * kRadix * sizeof(uint64_t)) != hipSuccess ||
+      hipMemset(c->scan_status, 0, nblk * sizeof(uint64_t)) != hipSuccess ||
       hipMemset(c->dc, 0, sizeof(DeviceCounters)) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     free_all(c);
@@ -327,7 +329,7 @@ int higs_project(higs_ctx* c, int64_t n, const float* means, const float* scales
     TimerScope ts(c, HIGS_TIMER_PROJECT, s);
     rc = hip_err(launch_project(n, means, scales, quats, opacities, sh, c->ca, c->pa, c->f_mx,
                                 c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau, c->f_key, c->f_cnt,
-                                c->rec, c->block_sums, s));
+                                c->rec, c->dc, s));
   }
   if (rc) return rc;
   c->stage = 1;
@@ -342,17 +344,15 @@ int higs_bin_sort(higs_ctx* c, void* stream) {
   c->last_stream = s;
   int rc;
   {
-    TimerScope ts(c, HIGS_TIMER_SCAN, s);
-    rc = hip_err(launch_scan(c->n > 0 ? c->n : 0, c->f_cnt, c->block_sums,
-                             (uint32_t)c->max_pairs, c->dc, s));
+    TimerScope ts(c, HIGS_TIMER_SCAN, s);  // the scan is folded into the fill
   }
-  if (rc) return rc;
   {
     TimerScope ts(c, HIGS_TIMER_FILL, s);
     rc = hip_err(launch_fill(c->n, c->ca, c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau,
-                             c->f_key, c->f_cnt, c->block_sums, (uint32_t)c->max_pairs, c->keys[0],
-                             c->vals[0], s));
+                             c->f_key, c->f_cnt, c->scan_status, c->scan_epoch,
+                             (uint32_t)c->max_pairs, c->dc, c->keys[0], c->vals[0], s));
   }
+  c->scan_epoch = c->scan_epoch + 1u >= (1u << 30) ? 1u : c->scan_epoch + 1u;
   if (rc) return rc;
   if ((c->debug_flags & HIGS_DEBUG_KEEP_PAIRS) && c->dbg_keys) {
     rc = hip_err(hipMemcpyAsync(c->dbg_keys, c->keys[0], (size_t)c->max_pairs * 8,
@@ -497,6 +497,15 @@ int higs_debug_copy(higs_ctx* c, int which, void* host_dst, size_t bytes) {
       }
       const size_t kb = bytes < np * 8 ? bytes : np * 8;
       if (hipMemcpy(dst, k, kb, hipMemcpyDeviceToHost) != hipSuccess) return HIGS_E_HIP;
+      // keys are stored range-compressed; hand them back as
+      // macro-tile << 32 | float32 depth bits
+      const uint32_t dbits = depth_bits(h.key_min, h.key_max);
+      uint64_t* hk = reinterpret_cast<uint64_t*>(dst);
+      for (size_t q = 0; q < kb / 8; ++q) {
+        const uint64_t mt = dbits >= 64 ? 0 : hk[q] >> dbits;
+        const uint64_t dep = hk[q] & ((dbits >= 64 ? 0ull : (1ull << dbits)) - 1ull);
+        hk[q] = (mt << 32) | (uint64_t)(uint32_t)(dep + h.key_min);
+      }
       if (bytes > np * 8 &&
           hipMemcpy(dst + np * 8, v, bytes - np * 8, hipMemcpyDeviceToHost) != hipSuccess)
         return HIGS_E_HIP;

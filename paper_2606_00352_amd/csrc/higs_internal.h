@@ -53,10 +53,28 @@ struct DeviceCounters {
   uint32_t raster_next;     // work counter of the persistent rasteriser
   uint32_t tile_next[kMaxPasses];  // work counters of the sort passes
   uint32_t sort_passes;     // radix passes that moved data (others skipped)
-  uint32_t pad0;
+  uint32_t fill_next;       // block counter of the emission kernel
   unsigned long long n_evals;  // gaussian-tile evaluations (when counted)
-  uint32_t pad[12];
+  uint32_t key_min;         // smallest / largest float32 depth bits of the
+  uint32_t key_max;         //   frame's visible gaussians (key compression)
+  uint32_t pad[10];
 };
+
+// Look-back status words (emission scan and sort passes): 30-bit epoch,
+// 2-bit flag, 32-bit count.
+constexpr uint32_t kFlagAggregate = 1u;
+constexpr uint32_t kFlagPrefix = 2u;
+constexpr uint32_t kMaxSpins = 1u << 22;  // look-back bound: every wave exits
+
+// Bits of (depth bits - key_min) in a pair key: enough for key_max - key_min.
+__host__ __device__ __forceinline__ uint32_t depth_bits(uint32_t kmin, uint32_t kmax) {
+  uint32_t d = kmax >= kmin ? kmax - kmin : 0u, b = 0;
+  while (d) {
+    ++b;
+    d >>= 1;
+  }
+  return b;
+}
 
 // Camera data passed by value to kernels.
 struct CamArgs {
@@ -80,15 +98,13 @@ hipError_t launch_project(int64_t n, const float* means, const float* scales, co
                           const float* opac, const float* sh, CamArgs cam, ParamArgs prm,
                           float* f_mx, float* f_my, float* f_a, float* f_b, float* f_c,
                           float* f_tau, uint32_t* f_key, uint32_t* f_cnt, RasterRecord* rec,
-                          uint32_t* block_sums, hipStream_t s);
-
-hipError_t launch_scan(int64_t n, const uint32_t* cnt, uint32_t* block_sums, uint32_t max_pairs,
-                       DeviceCounters* dc, hipStream_t s);
+                          DeviceCounters* dc, hipStream_t s);
 
 hipError_t launch_fill(int64_t n, CamArgs cam, const float* f_mx, const float* f_my,
                        const float* f_a, const float* f_b, const float* f_c, const float* f_tau,
-                       const uint32_t* f_key, const uint32_t* f_cnt, const uint32_t* block_offsets,
-                       uint32_t max_pairs, uint64_t* keys, uint32_t* vals, hipStream_t s);
+                       const uint32_t* f_key, const uint32_t* f_cnt, uint64_t* scan_status,
+                       uint32_t epoch, uint32_t max_pairs, DeviceCounters* dc, uint64_t* keys,
+                       uint32_t* vals, hipStream_t s);
 
 struct SortBuffers {
   uint64_t* keys[2];

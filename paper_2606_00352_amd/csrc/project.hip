@@ -8,12 +8,11 @@
 // discrete decisions downstream (pair lists, depth order, batches) depend only
 // on these fields, so they can be reproduced bit for bit.  The SH colour runs
 // in float32.  The same thread counts the gaussian's macro-tile pairs
-// (predicate.h), the wave records a 64-bit visibility ballot, and the block
-// writes the sums of its pair counts and visible gaussians for the emission
-// scan.
+// (predicate.h), and the block folds the depth bits of its visible gaussians
+// into the frame's [min, max] (used to compress the sort keys).
 //
 // Outputs: SoA binning fields (coalesced), a 48-byte raster record per
-// visible gaussian, per-gaussian pair counts and per-block count sums.
+// visible gaussian, per-gaussian pair counts.
 #include "higs_internal.h"
 #include "predicate.h"
 
@@ -176,10 +175,11 @@ project_kernel(int64_t n, const float* __restrict__ means, const float* __restri
                float* __restrict__ f_mx, float* __restrict__ f_my, float* __restrict__ f_a,
                float* __restrict__ f_b, float* __restrict__ f_c, float* __restrict__ f_tau,
                uint32_t* __restrict__ f_key, uint32_t* __restrict__ f_cnt,
-               RasterRecord* __restrict__ rec, uint32_t* __restrict__ block_sums) {
-  __shared__ uint32_t wave_sums[2][kProjBlock / 64];
+               RasterRecord* __restrict__ rec, DeviceCounters* __restrict__ dc) {
+  __shared__ uint32_t wave_min[kProjBlock / 64], wave_max[kProjBlock / 64];
   const int64_t i = (int64_t)blockIdx.x * kProjBlock + threadIdx.x;
   uint32_t cnt = 0;
+  uint32_t kmin = 0xffffffffu, kmax = 0u;
   if (i < n) {
     const float3 mean = make_float3(means[3 * i + 0], means[3 * i + 1], means[3 * i + 2]);
     const float3 scale = make_float3(scales[3 * i + 0], scales[3 * i + 1], scales[3 * i + 2]);
@@ -205,6 +205,8 @@ project_kernel(int64_t n, const float* __restrict__ means, const float* __restri
       f_c[i] = f.c;
       f_tau[i] = f.tau;
       if (cnt > 0) {
+        kmin = key;
+        kmax = key;
         const int ncoef = (prm.sh_degree + 1) * (prm.sh_degree + 1);
         float dx = mean.x - campos.x, dy = mean.y - campos.y, dz = mean.z - campos.z;
         const float dn2 = dx * dx + dy * dy + dz * dz;
@@ -237,22 +239,28 @@ project_kernel(int64_t n, const float* __restrict__ means, const float* __restri
     f_key[i] = key;
     f_cnt[i] = cnt;
   }
-  // block sum of the pair counts, for the emission scan
-  uint32_t s = cnt;
+  // frame-wide range of the visible depth bits
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  const uint32_t vis = (uint32_t)__popcll(__ballot(cnt > 0));
+  for (int off = 32; off > 0; off >>= 1) {
+    kmin = min(kmin, (uint32_t)__shfl_xor(kmin, off, 64));
+    kmax = max(kmax, (uint32_t)__shfl_xor(kmax, off, 64));
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) {
-    wave_sums[0][wave] = s;
-    wave_sums[1][wave] = vis;
+    wave_min[wave] = kmin;
+    wave_max[wave] = kmax;
   }
   __syncthreads();
-  if (threadIdx.x < 2) {
-    uint32_t tot = 0;
+  if (threadIdx.x == 0) {
 #pragma unroll
-    for (int w = 0; w < kProjBlock / 64; ++w) tot += wave_sums[threadIdx.x][w];
-    block_sums[2 * blockIdx.x + threadIdx.x] = tot;
+    for (int w = 1; w < kProjBlock / 64; ++w) {
+      kmin = min(kmin, wave_min[w]);
+      kmax = max(kmax, wave_max[w]);
+    }
+    if (kmin <= kmax) {
+      atomicMin(&dc->key_min, kmin);
+      atomicMax(&dc->key_max, kmax);
+    }
   }
 }
 
@@ -260,7 +268,7 @@ hipError_t launch_project(int64_t n, const float* means, const float* scales, co
                           const float* opac, const float* sh, CamArgs cam, ParamArgs prm,
                           float* f_mx, float* f_my, float* f_a, float* f_b, float* f_c,
                           float* f_tau, uint32_t* f_key, uint32_t* f_cnt, RasterRecord* rec,
-                          uint32_t* block_sums, hipStream_t s) {
+                          DeviceCounters* dc, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   // camera centre, -R^T t, for the SH view direction
   float3 campos;
@@ -270,7 +278,7 @@ hipError_t launch_project(int64_t n, const float* means, const float* scales, co
   const unsigned blocks = (unsigned)((n + kProjBlock - 1) / kProjBlock);
   hipLaunchKernelGGL(project_kernel, dim3(blocks), dim3(kProjBlock), 0, s, n, means, scales,
                      quats, opac, sh, cam, prm, campos, f_mx, f_my,
-                     f_a, f_b, f_c, f_tau, f_key, f_cnt, rec, block_sums);
+                     f_a, f_b, f_c, f_tau, f_key, f_cnt, rec, dc);
   return hipGetLastError();
 }
 

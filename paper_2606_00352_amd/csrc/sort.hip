@@ -30,29 +30,35 @@ __device__ __forceinline__ void st_status(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-constexpr uint32_t kMaxSpins = 1u << 22;  // look-back bound: every wave exits
-constexpr uint32_t kFlagAggregate = 1u;
-constexpr uint32_t kFlagPrefix = 2u;
 __device__ __forceinline__ uint64_t status_word(uint32_t epoch, uint32_t flag, uint32_t count) {
   return ((uint64_t)epoch << 34) | ((uint64_t)flag << 32) | (uint64_t)count;
 }
 
 constexpr int kHistThreads = 256;
+constexpr int kHistCopies = 8;  // LDS copies: lanes l and l+8k share one, 8-way at worst
 __global__ void __launch_bounds__(kHistThreads)
 sort_hist_kernel(const uint64_t* __restrict__ keys, const DeviceCounters* __restrict__ dc,
                  int n_passes, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[kMaxPasses * kRadix];
-  for (int k = threadIdx.x; k < n_passes * kRadix; k += kHistThreads) h[k] = 0;
+  // the top digits of a frame's keys take few values: spreading the counters
+  // over copies keeps the LDS atomics of one wave from piling on one address
+  __shared__ uint32_t h[kHistCopies][kMaxPasses * kRadix];
+  for (int k = threadIdx.x; k < kHistCopies * kMaxPasses * kRadix; k += kHistThreads)
+    (&h[0][0])[k] = 0;
   __syncthreads();
   const uint32_t n = dc->n_pairs;
+  uint32_t* mine = h[threadIdx.x & (kHistCopies - 1)];
   for (uint32_t i = blockIdx.x * kHistThreads + threadIdx.x; i < n; i += gridDim.x * kHistThreads) {
     const uint64_t key = keys[i];
     for (int p = 0; p < n_passes; ++p)
-      atomicAdd(&h[p * kRadix + (uint32_t)((key >> (kRadixBits * p)) & (kRadix - 1))], 1u);
+      atomicAdd(&mine[p * kRadix + (uint32_t)((key >> (kRadixBits * p)) & (kRadix - 1))], 1u);
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < n_passes * kRadix; k += kHistThreads)
-    if (h[k]) atomicAdd(&hist[k], h[k]);
+  for (int k = threadIdx.x; k < n_passes * kRadix; k += kHistThreads) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int c = 0; c < kHistCopies; ++c) v += h[c][k];
+    if (v) atomicAdd(&hist[k], v);
+  }
 }
 
 // One block of 256 threads (one per digit): per pass, skip flag, source
@@ -96,8 +102,11 @@ constexpr int kWaves = kSortThreads / 64;
 constexpr int kWaveItems = 64 * kSortItems;  // 1024 keys per wave
 
 struct SortLds {
-  uint64_t keys[kSortTile];
-  uint32_t vals[kSortTile];
+  // the tile regrouped by digit: keys first, then (reusing the space) values
+  union {
+    uint64_t keys[kSortTile];
+    uint32_t vals[kSortTile];
+  } buf;
   uint32_t whist[kWaves][kRadix];  // per-wave digit counts, then wave prefixes
   uint32_t local_start[kRadix];    // first LDS slot of each digit in the tile
   uint32_t gbase[kRadix];          // global position of LDS slot 0 of each digit
@@ -212,24 +221,36 @@ onesweep_kernel(int pass, uint32_t epoch, uint64_t* __restrict__ k0, uint32_t* _
       L.gbase[d] = base[pass * kRadix + d] + prefix - ls;
     }
     __syncthreads();
-    // regroup by digit in LDS
+    // regroup by digit in LDS: keys, then values through the same buffer
+    uint32_t slot[kSortItems];
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
       const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-      const uint32_t slot = L.local_start[d] + L.whist[wave][d] + rank[k];
-      L.keys[slot] = key[k];
-      L.vals[slot] = val[k];
+      slot[k] = L.local_start[d] + L.whist[wave][d] + rank[k];
+      L.buf.keys[slot[k]] = key[k];
     }
     __syncthreads();
     const uint32_t valid = min((uint32_t)kSortTile, n - t0);
-    for (uint32_t j = tid; j < valid; j += kSortThreads) {
-      const uint64_t kk = L.keys[j];
-      const uint32_t d = (uint32_t)(kk >> shift) & (kRadix - 1);
-      const uint32_t dst = L.gbase[d] + j;
-      if (dst < n) {
-        kout[dst] = kk;
-        vout[dst] = L.vals[j];
+    uint32_t dst[kSortItems];
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+      const uint32_t j = tid + k * kSortThreads;
+      dst[k] = 0xffffffffu;
+      if (j < valid) {
+        const uint64_t kk = L.buf.keys[j];
+        const uint32_t d = (uint32_t)(kk >> shift) & (kRadix - 1);
+        dst[k] = L.gbase[d] + j;
+        if (dst[k] < n) kout[dst[k]] = kk;
       }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) L.buf.vals[slot[k]] = val[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+      const uint32_t j = tid + k * kSortThreads;
+      if (j < valid && dst[k] < n) vout[dst[k]] = L.buf.vals[j];
     }
     __syncthreads();
   }
