@@ -34,6 +34,35 @@ PROJECT_B_PER_VISIBLE = 192 + 24 + 48
 # test, weight, three colour FMAs, transmittance update).
 RASTER_OPS_PER_EVAL = 16
 
+# Bytes per copy for the counter calibration: one plain device-to-device copy
+# of this size runs before the warm-up, so that FETCH_SIZE / WRITE_SIZE read
+# in a `rocprofv3 --pmc` run of this script can be scaled to bytes.
+COPY_CALIBRATION_BYTES = 1 << 30
+
+# HBM traffic per launch of the dominant kernel, from two `rocprofv3 --pmc`
+# runs of this script (FETCH_SIZE, then WRITE_SIZE; mean over the timed frames,
+# scaled by the same counters' reading for the calibration copy).  Keyed by the
+# SHA-256 of the kernel's source file at the time the counters were taken: if
+# the source differs, the figure no longer describes the kernel and is
+# reported as null.
+MEASURED_TRAFFIC = {}
+KERNEL_SOURCES = {"project": "project.hip", "fill": "emit.hip", "sort": "sort.hip",
+                  "raster": "raster.hip"}
+
+
+def kernel_source_sha(kernel):
+    import hashlib
+    path = os.path.join(ROOT, "paper_2606_00352_amd", "csrc", KERNEL_SOURCES[kernel])
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel):
+    m = MEASURED_TRAFFIC.get(kernel)
+    if not m or m["src_sha256"] != kernel_source_sha(kernel):
+        return None
+    return m["bytes_per_launch"]
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -84,6 +113,13 @@ def main():
     log(f"scene: {scene.n} gaussians generated in {time.perf_counter() - t:.1f} s")
     tens = higs.scene_tensors(scene, "cuda:0")
     torch.cuda.synchronize()
+    # counter calibration: one plain copy of known size (see COPY_CALIBRATION_BYTES)
+    src = torch.ones(COPY_CALIBRATION_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
     # size the context from a first frame of every view (grow on overflow)
     max_pairs = 3 * scene.n
@@ -138,13 +174,17 @@ def main():
     mean = {k: float(np.mean(v)) for k, v in sizes.items()}
     n = scene.n
     rl = {}
+    # fill: reads the pair count of every gaussian (4 B) and the six binning
+    # fields and depth key of every visible one (28 B); writes 12 B per pair
+    fill_bytes = 4 * n + 28 * mean["visible"] + 12 * mean["pairs"]
+    rl["fill"] = ("hbm", fill_bytes / (timers["fill"] * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", fill_bytes)
     proj_bytes = PROJECT_B_PER_GAUSSIAN * n + PROJECT_B_PER_VISIBLE * mean["visible"]
     rl["project"] = ("hbm", proj_bytes / (timers["project"] * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", proj_bytes)
     sort_bytes = mean["pairs"] * (8 + 24 * mean["passes"])
     rl["sort"] = ("hbm", sort_bytes / (timers["sort"] * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", sort_bytes)
     ops = mean["evals"] * RASTER_OPS_PER_EVAL
     rl["raster"] = ("alu", ops / (timers["raster"] * 1e-3) / 1e12, VALU_PEAK_TOPS, "Tops/s", ops)
-    dom = max(("project", "sort", "raster"), key=lambda k: timers[k])
+    dom = max(("project", "fill", "sort", "raster"), key=lambda k: timers[k])
     bound, ach, peak, unit, work = rl[dom]
     for k, (b, a, p, u, w) in rl.items():
         log(f"{k}: {a:.1f} {u} of {p:.1f} ({100 * a / p:.1f}%)")
@@ -166,9 +206,13 @@ def main():
                    "mean_visible": round(mean["visible"]), "mean_pairs": round(mean["pairs"]),
                    "mean_batches": round(mean["batches"]), "mean_sort_passes": mean["passes"],
                    "kernel_ms": {k: round(v, 4) for k, v in timers.items()},
-                   "sort_pairs_per_s": round(mean["pairs"] / (timers["sort"] * 1e-3))},
+                   "sort_pairs_per_s": round(mean["pairs"] / (timers["sort"] * 1e-3)),
+                   "stage_roofline": {k: {"bound": b, "achieved": round(a, 2), "peak": round(p, 2),
+                                          "unit": u, "frac": round(a / p, 4),
+                                          "traffic": measured_traffic(k)}
+                                      for k, (b, a, p, u, w) in rl.items()}},
         "roofline": {"kernel": dom, "bound": bound, "achieved": round(ach, 2), "peak": round(peak, 2),
-                     "unit": unit, "frac": round(ach / peak, 4), "traffic": None},
+                     "unit": unit, "frac": round(ach / peak, 4), "traffic": measured_traffic(dom)},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

@@ -1,4 +1,5 @@
-"""Python front of the plain FP64 CPU oracle (higs_oracle.c).
+"""Python front of the plain FP64 CPU oracle (higs_oracle.c, and its adjoint
+in higs_oracle_grad.c).
 
 TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke entry point and the
 benchmark's CPU-baseline leg, never by the GPU library or its binding.  The
@@ -19,7 +20,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "higs_oracle.c")
+_SRCS = [os.path.join(_HERE, f) for f in ("higs_oracle.c", "higs_oracle_grad.c", "higs_oracle.h")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 TILE = 8
@@ -30,14 +31,17 @@ AMB_ALPHA, AMB_T = 1, 2
 # columns of the per-gaussian double record
 G_TZ, G_MX, G_MY, G_A, G_B, G_C, G_TAU, G_L0, G_L1, G_L2, G_OP, G_R, G_G, G_BL = range(14)
 G_NCOL = 14
+# columns of the per-gaussian gradient with respect to the raster record
+D_MX, D_MY, D_L0, D_L1, D_L2, D_OP, D_R, D_G, D_BL = range(9)
+D_NCOL = 9
 
 
 def build(force: bool = False) -> str:
     """Compiles the oracle with gcc (double precision, no contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(s) for s in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+               "-fPIC", "-shared", "-o", tmp] + [s for s in _SRCS if s.endswith(".c")] + ["-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)
     return _LIB
@@ -97,6 +101,10 @@ def lib():
             "oc_sh_basis": (None, [P, ctypes.c_int, P]),
             "oc_depth_key": (ctypes.c_uint32, [ctypes.c_double]),
             "oc_num_threads": (ctypes.c_int, []),
+            "oc_sh_basis_grad": (None, [P, ctypes.c_int, P]),
+            "oc_project_grad": (None, [i64, P, P, P, P, P, P, P, P, P, P, P, P, P]),
+            "oc_render_tiled_grad": (None, [P, P, P, i64, P, P, P, P, P]),
+            "oc_render_tiled_signature": (ctypes.c_uint64, [P, P, P, i64, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -284,3 +292,62 @@ def frame(scene, cam, params: Params = None, render: bool = True, pixels=None) -
     if render:
         fr.image, fr.T, fr.amb = render_tiled(geo, sgid, mt_off, tab, cam, params, pixels)
     return fr
+
+
+# ------------------------------------------------------------------ adjoint --
+def sh_basis_grad(direction, degree: int = 3) -> np.ndarray:
+    """[16, 3]: d Y_k / d(x, y, z), components taken as independent."""
+    d = np.ascontiguousarray(np.asarray(direction, dtype=np.float64).reshape(3))
+    out = np.zeros((16, 3), dtype=np.float64)
+    lib().oc_sh_basis_grad(_p(d), degree, _p(out))
+    return out
+
+
+def render_grad(geo, sorted_gid, tab, cam, dimg, dT=None, params: Params = None) -> np.ndarray:
+    """dL/d(raster record) [N, 9] (columns D_*) of the batched render, from
+    dL/dimage [H, W, 3] and dL/dT [H, W] (None: zero)."""
+    params = params or Params()
+    dgeo = np.zeros((geo.shape[0], D_NCOL), dtype=np.float64)
+    dimg = np.ascontiguousarray(dimg, dtype=np.float64).reshape(cam.height, cam.width, 3)
+    dT_ = None if dT is None else np.ascontiguousarray(dT, dtype=np.float64).reshape(cam.height, cam.width)
+    c, p = _cam(cam), params.c()
+    sorted_gid = np.ascontiguousarray(sorted_gid, dtype=np.int32)
+    tab = np.ascontiguousarray(tab, dtype=np.int32)
+    lib().oc_render_tiled_grad(_p(geo), _p(sorted_gid), _p(tab), tab.shape[0], ctypes.byref(c),
+                               ctypes.byref(p), _p(dimg), None if dT_ is None else _p(dT_), _p(dgeo))
+    return dgeo
+
+
+def render_signature(geo, sorted_gid, tab, cam, params: Params = None) -> int:
+    """Digest of every discrete decision of the batched render."""
+    params = params or Params()
+    c, p = _cam(cam), params.c()
+    sorted_gid = np.ascontiguousarray(sorted_gid, dtype=np.int32)
+    tab = np.ascontiguousarray(tab, dtype=np.int32)
+    return int(lib().oc_render_tiled_signature(_p(geo), _p(sorted_gid), _p(tab), tab.shape[0],
+                                               ctypes.byref(c), ctypes.byref(p)))
+
+
+def project_grad(scene, cam, valid, dgeo, params: Params = None) -> dict:
+    """Gradients of the scene inputs from dL/d(raster record)."""
+    params = params or Params()
+    means, scales, quats, opac, sh = (np.ascontiguousarray(a, dtype=np.float32) for a in scene.arrays())
+    n = means.shape[0]
+    ncoef = (params.sh_degree + 1) ** 2
+    sh = np.ascontiguousarray(sh[:, :ncoef, :])
+    out = {"means": np.zeros((n, 3)), "scales": np.zeros((n, 3)), "quats": np.zeros((n, 4)),
+           "opacities": np.zeros(n), "sh": np.zeros((n, ncoef, 3))}
+    c, p = _cam(cam), params.c()
+    dgeo = np.ascontiguousarray(dgeo, dtype=np.float64)
+    lib().oc_project_grad(n, _p(means), _p(scales), _p(quats), _p(sh), ctypes.byref(c), ctypes.byref(p),
+                          _p(valid), _p(dgeo), _p(out["means"]), _p(out["scales"]), _p(out["quats"]),
+                          _p(out["opacities"]), _p(out["sh"]))
+    return out
+
+
+def frame_grad(scene, cam, dimg, dT=None, params: Params = None, fr: Frame = None):
+    """The adjoint of the whole forward path: returns (frame, dgeo, grads)."""
+    params = params or Params()
+    fr = fr or frame(scene, cam, params)
+    dgeo = render_grad(fr.geo, fr.sorted_gid, fr.batch_tab, cam, dimg, dT, params)
+    return fr, dgeo, project_grad(scene, cam, fr.valid, dgeo, params)

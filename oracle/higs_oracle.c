@@ -41,35 +41,7 @@
 #include <omp.h>
 #endif
 
-#define OC_TILE 8          /* render tile edge, pixels (sec. 3.1) */
-#define OC_MT_TX 8         /* macro-tile width in render tiles */
-#define OC_MT_TY 4         /* macro-tile height in render tiles */
-#define OC_MT_W (OC_TILE * OC_MT_TX) /* 64 px */
-#define OC_MT_H (OC_TILE * OC_MT_TY) /* 32 px */
-
-/* Columns of the per-gaussian double record written by oc_project. */
-enum {
-  G_TZ = 0, G_MX, G_MY, G_A, G_B, G_C, G_TAU, G_L0, G_L1, G_L2, G_OP,
-  G_R, G_G, G_BL, G_NCOL
-};
-
-typedef struct {
-  int32_t width, height;
-  float fx, fy, cx, cy;
-  float world_to_cam[12]; /* row-major [R | t], x_cam = R x_world + t */
-  float background[3];
-} oc_camera;
-
-typedef struct {
-  double near_z;     /* cull when camera-space z <= near_z */
-  double alpha_min;  /* skip contributions with alpha below it; the opacity
-                        level tau assumes the paper's 1/255 */
-  double alpha_max;  /* 0.99 clamp on alpha */
-  double t_eps;      /* stop once transmittance < t_eps (after compositing) */
-  double dilation;   /* added to the diagonal of the 2D covariance */
-  int32_t batch_cap; /* B_r */
-  int32_t sh_degree; /* 0..3 */
-} oc_params;
+#include "higs_oracle.h"
 
 static int is_finite_d(double v) { return isfinite(v) != 0; }
 
@@ -425,11 +397,6 @@ int64_t oc_batches(int64_t np, const int32_t* sorted_mt, int32_t n_mt, int32_t c
 }
 
 /* --------------------------------------------------------- raster ---- */
-/* Flags for a pixel whose GPU result may legitimately differ from this
- * oracle by more than rounding: a contribution decided at alpha ~ alpha_min,
- * or a transmittance landing next to t_eps. */
-#define OC_AMB_ALPHA 1
-#define OC_AMB_T 2
 
 static double alpha_at(const double* rec, double px, double py, const oc_params* prm,
                        uint8_t* amb) {
