@@ -91,6 +91,48 @@ def cpu_baseline(scene, cam, row_stride=2):
                       f"pixel row ({len(pix)} px, {t2 - t1:.1f} s), frame time extrapolated to all rows"}
 
 
+def backward_leg(n=1_000_000, warmup=5, steps=20):
+    """Differentiable render at its workload size (1M clustered gaussians,
+    1920x1080, view 0 of the orbit): mean ms of forward-only frames and of
+    forward + adjoint (higs_raster_backward) frames, HIP-synchronised."""
+    import numpy as np
+    import torch
+    from paper_2606_00352_amd import higs, scenes
+    scene = scenes.clustered_scene(n, seed=4)
+    cam = scenes.orbit_cameras(60, 101, 1920, 1080, 1100.0)[0]
+    tens = higs.scene_tensors(scene, "cuda:0")
+    ctx = higs.Context(scene.n, 1920, 1080)
+    image = torch.empty((1080, 1920, 3), dtype=torch.float32, device="cuda:0")
+    T = torch.empty((1080, 1920), dtype=torch.float32, device="cuda:0")
+    rng = np.random.default_rng(40)
+    dimg = torch.from_numpy(rng.uniform(-1, 1, (1080, 1920, 3)).astype(np.float32)).cuda()
+    outs = [torch.empty_like(t) for t in tens]
+
+    def fwd():
+        ctx.render(*tens, cam, image, T)
+
+    def fwd_bwd():
+        fwd()
+        ctx.raster_backward(dimg, None, *outs)
+
+    res = {}
+    for name, fn in (("forward_ms", fwd), ("forward_backward_ms", fwd_bwd)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = round((time.perf_counter() - t0) * 1e3 / steps, 4)
+    c = ctx.counts()
+    assert c.overflow == 0
+    res["backward_ms"] = round(res["forward_backward_ms"] - res["forward_ms"], 4)
+    res["workload"] = f"{n} clustered gaussians, 1920x1080, gradients of all parameters"
+    res["pairs"] = int(c.n_pairs)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +140,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--gaussians", type=int, default=5_800_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the frame path is single-GPU; --gpus must be 1", file=sys.stderr)
@@ -214,6 +257,11 @@ def main():
         "roofline": {"kernel": dom, "bound": bound, "achieved": round(ach, 2), "peak": round(peak, 2),
                      "unit": unit, "frac": round(ach / peak, 4), "traffic": measured_traffic(dom)},
     }
+    if not args.no_backward:
+        log("backward leg")
+        del ctx
+        result["backward"] = backward_leg()
+        log(f"backward: {result['backward']}")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(scene, cams[0])

@@ -17,6 +17,10 @@
  *                   macro-tile (sec. 3.4, Algorithms 1 and 2) and the
  *                   post-blend merge of the batch partials with Eq. 1.
  *   higs_render   - all of the above in one call.
+ *   higs_raster_backward - the adjoint of the last frame: gradients of a loss
+ *                   on the image (and final transmittance) with respect to
+ *                   the gaussian parameters (the backward that the paper's
+ *                   Forward-only paragraph outlines).
  *
  * Conventions shared by every entry point:
  *   - Array arguments are DEVICE pointers to contiguous row-major float32
@@ -153,6 +157,35 @@ int higs_render(higs_ctx* ctx, int64_t n, const float* means, const float* scale
                 const float* quats, const float* opacities, const float* sh,
                 const higs_camera* cam, float* image, float* T_out, void* stream);
 
+/* Adjoint of the last frame rendered on ctx (the paper is forward-only; its
+ * Forward-only paragraph outlines this backward: the post-blend merge of
+ * Eq. 1 becomes a prefix scan of transmittance over the batches, the point
+ * where transmittance saturates is recovered per (pixel, batch), and the
+ * blend is reversed by dividing by (1 - alpha) in float32).
+ *   dL_dimage  [H, W, 3] float32: gradient of the loss with respect to the
+ *              image higs_raster wrote (H, W of that frame's camera).
+ *   dL_dT      [H, W] float32 or NULL (zero): gradient with respect to the
+ *              final transmittance T_out.
+ *   dmeans [n, 3], dscales [n, 3], dquats [n, 4], dopacities [n],
+ *   dsh [n, (sh_degree + 1)^2, 3]: outputs, written in full (zero for
+ *              culled and off-screen gaussians); gradients with respect to
+ *              the arrays given to higs_project, in their layouts (scales
+ *              linear, opacities after the sigmoid, quaternions as given,
+ *              unnormalised).
+ * The scene arrays passed to the frame's higs_project must still hold the
+ * same values: the adjoint re-reads them.  The discrete structure (culls,
+ * pairs, depth order, batches, which gaussians composite at a pixel, the
+ * alpha clamp at alpha_max) is held fixed, as its derivative is zero almost
+ * everywhere.  Per-gaussian sums are accumulated with float atomics, so
+ * results vary in the last bits from run to run.  Needs a completed
+ * higs_raster on ctx since its last higs_project (else HIGS_E_STATE); the
+ * first call allocates the adjoint's buffers (max_batches * 16 KiB +
+ * max_gaussians * 64 B; HIGS_E_NOMEM if that fails).  Outputs are undefined
+ * when the frame overflowed its capacities (higs_get_counts). */
+int higs_raster_backward(higs_ctx* ctx, const float* dL_dimage, const float* dL_dT,
+                         float* dmeans, float* dscales, float* dquats, float* dopacities,
+                         float* dsh, void* stream);
+
 /* Synchronises the stream of the last call and reports the frame's sizes. */
 int higs_get_counts(higs_ctx* ctx, higs_counts* out);
 
@@ -191,7 +224,7 @@ int higs_debug_copy(higs_ctx* ctx, int which, void* host_dst, size_t bytes);
  * any host synchronisation; higs_get_timers synchronises and writes the mean
  * over those frames, ms[HIGS_TIMER_*] in milliseconds. */
 #define HIGS_TIMER_PROJECT 0 /* projection + SH + per-gaussian pair counts */
-#define HIGS_TIMER_SCAN 1    /* the scan runs inside the fill: this slot reads ~0 */
+#define HIGS_TIMER_SCAN 1    /* exclusive scan of the per-block pair counts */
 #define HIGS_TIMER_FILL 2    /* pair emission */
 #define HIGS_TIMER_SORT 3    /* all radix-sort kernels */
 #define HIGS_TIMER_BATCH 4   /* macro-tile offsets + batch table */

@@ -105,6 +105,7 @@ def lib():
             "oc_project_grad": (None, [i64, P, P, P, P, P, P, P, P, P, P, P, P, P]),
             "oc_render_tiled_grad": (None, [P, P, P, i64, P, P, P, P, P]),
             "oc_render_tiled_signature": (ctypes.c_uint64, [P, P, P, i64, P, P]),
+            "oc_render_tiled_ambiguous": (i64, [i64, P, P, P, i64, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -326,6 +327,19 @@ def render_signature(geo, sorted_gid, tab, cam, params: Params = None) -> int:
     tab = np.ascontiguousarray(tab, dtype=np.int32)
     return int(lib().oc_render_tiled_signature(_p(geo), _p(sorted_gid), _p(tab), tab.shape[0],
                                                ctypes.byref(c), ctypes.byref(p)))
+
+
+def ambiguous_gaussians(geo, sorted_gid, tab, cam, params: Params = None) -> np.ndarray:
+    """uint8 [N]: 1 for gaussians with an evaluation whose alpha decision
+    (against 1/255 or the alpha_max clamp) float32 may take the other way."""
+    params = params or Params()
+    gmask = np.zeros(geo.shape[0], dtype=np.uint8)
+    c, p = _cam(cam), params.c()
+    sorted_gid = np.ascontiguousarray(sorted_gid, dtype=np.int32)
+    tab = np.ascontiguousarray(tab, dtype=np.int32)
+    lib().oc_render_tiled_ambiguous(geo.shape[0], _p(geo), _p(sorted_gid), _p(tab), tab.shape[0],
+                                    ctypes.byref(c), ctypes.byref(p), _p(gmask))
+    return gmask
 
 
 def project_grad(scene, cam, valid, dgeo, params: Params = None) -> dict:

@@ -398,6 +398,21 @@ int64_t oc_batches(int64_t np, const int32_t* sorted_mt, int32_t n_mt, int32_t c
 
 /* --------------------------------------------------------- raster ---- */
 
+/* How far a float32 evaluation of q can land from this double one: the
+ * rasteriser works on the float32 roundings of the centre and the Cholesky
+ * factors (half an ulp each, at unit roundoff 2^-24), forms u, v and q in
+ * float32, and takes alpha through a prescaled exp2 (a few ulps, i.e. a few
+ * units of 2^-24 in q).  Used to flag the decisions (alpha >= 1/255, the
+ * alpha clamp) that float32 may take the other way. */
+double oc_f32_q_bound(const double* rec, double dx, double dy, double u, double v, double q) {
+  const double e = 1.0 / 16777216.0;
+  double emx = fabs(rec[G_MX]) * e, emy = fabs(rec[G_MY]) * e;
+  double du = fabs(rec[G_L0]) * emx + fabs(rec[G_L1]) * emy +
+              (fabs(rec[G_L0] * dx) + fabs(rec[G_L1] * dy)) * 3.0 * e;
+  double dv = fabs(rec[G_L2]) * emy + fabs(rec[G_L2] * dy) * 2.0 * e;
+  return 2.0 * fabs(u) * du + 2.0 * fabs(v) * dv + (q + 4.0) * 4.0 * e;
+}
+
 static double alpha_at(const double* rec, double px, double py, const oc_params* prm,
                        uint8_t* amb) {
   double dx = px - rec[G_MX], dy = py - rec[G_MY];
@@ -405,7 +420,8 @@ static double alpha_at(const double* rec, double px, double py, const oc_params*
   double v = rec[G_L2] * dy;
   double q = u * u + v * v;
   double tau = rec[G_TAU];
-  if (fabs(q - tau) <= 1e-5 * (1.0 + tau)) *amb |= OC_AMB_ALPHA;
+  if (fabs(q - tau) <= 2.0 * oc_f32_q_bound(rec, dx, dy, u, v, q) + 1e-5 * (1.0 + tau))
+    *amb |= OC_AMB_ALPHA;
   double al = rec[G_OP] * exp(-0.5 * q);
   if (al > prm->alpha_max) al = prm->alpha_max;
   return al;

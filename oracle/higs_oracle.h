@@ -44,6 +44,7 @@ typedef struct {
 #define OC_AMB_T 2
 
 void oc_sh_basis(const double d[3], int degree, double out[16]);
+double oc_f32_q_bound(const double* rec, double dx, double dy, double u, double v, double q);
 uint32_t oc_depth_key(double tz);
 
 #endif

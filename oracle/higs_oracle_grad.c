@@ -478,3 +478,56 @@ uint64_t oc_render_tiled_signature(const double* geo, const int32_t* sorted_gid,
   free(first);
   return sig;
 }
+
+/* Marks (gmask[gid] = 1) every gaussian with an evaluation, at some pixel
+ * before that pixel's early stop, whose discrete decision float32 may take
+ * the other way: alpha against alpha_min (|q - tau| within the float32 bound
+ * of q), or o exp(-q/2) against the alpha_max clamp (within the same bound,
+ * as a relative change of alpha of half of it).  Such a gaussian's own
+ * gradient can legitimately jump between a float32 and this double adjoint.
+ * Returns how many gaussians are marked. */
+int64_t oc_render_tiled_ambiguous(int64_t n, const double* geo, const int32_t* sorted_gid,
+                                  const int32_t* batch_tab, int64_t nbatches,
+                                  const oc_camera* cam, const oc_params* prm, uint8_t* gmask) {
+  int32_t nmx = (cam->width + OC_MT_W - 1) / OC_MT_W;
+  int32_t nmy = (cam->height + OC_MT_H - 1) / OC_MT_H;
+  int64_t* first = first_batches(batch_tab, nbatches, nmx * nmy);
+  int64_t total = (int64_t)cam->width * cam->height;
+  memset(gmask, 0, (size_t)n);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t p = 0; p < total; ++p) {
+    int32_t x = (int32_t)(p % cam->width), y = (int32_t)(p / cam->width);
+    int32_t m = (y / OC_MT_H) * nmx + (x / OC_MT_W);
+    double px = x + 0.5, py = y + 0.5;
+    double Tacc = 1.0;
+    for (int64_t bi = first[m]; bi < first[m + 1]; ++bi) {
+      if (Tacc < prm->t_eps) break;
+      const int32_t* bt = batch_tab + 3 * bi;
+      double Tloc = 1.0;
+      for (int32_t k = 0; k < bt[2]; ++k) {
+        if (Tloc < prm->t_eps) break;
+        int32_t gid = sorted_gid[bt[1] + k];
+        const double* rec = geo + (int64_t)gid * G_NCOL;
+        double dx = px - rec[G_MX], dy = py - rec[G_MY];
+        double u = rec[G_L0] * dx + rec[G_L1] * dy, v = rec[G_L2] * dy;
+        double q = u * u + v * v;
+        double bound = 2.0 * oc_f32_q_bound(rec, dx, dy, u, v, q) + 1e-5 * (1.0 + rec[G_TAU]);
+        double raw = rec[G_OP] * exp(-0.5 * q);
+        int amb = fabs(q - rec[G_TAU]) <= bound ||
+                  fabs(raw - prm->alpha_max) <= prm->alpha_max * 0.5 * bound;
+        if (amb) {
+#pragma omp atomic write
+          gmask[gid] = 1;
+        }
+        double al = raw > prm->alpha_max ? prm->alpha_max : raw;
+        if (al < prm->alpha_min) continue;
+        Tloc = Tloc * (1.0 - al);
+      }
+      Tacc = Tacc * Tloc;
+    }
+  }
+  free(first);
+  int64_t cnt = 0;
+  for (int64_t i = 0; i < n; ++i) cnt += gmask[i];
+  return cnt;
+}

@@ -1,16 +1,14 @@
 // Stage 2a: (macro-tile, gaussian) pair emission (sec. 3.2 and sec. 4.3:
 // count, prefix sum, fill).
 //
-// The per-gaussian pair counts come from the projection kernel.  `fill_kernel`
-// claims its 256-gaussian blocks in order from a device counter, scans the
-// counts inside the block with wave prefix sums, and turns the block total
-// into a global offset with a decoupled look-back over the preceding blocks
-// (each block publishes its total, then its inclusive prefix, in an
-// epoch-tagged 64-bit word): one pass, no separate scan kernel.  It then re-runs
-// the intersection of each gaussian from the stored float32 fields (the count
-// pass's exact decisions) and writes pairs in gaussian-id order, macro-tiles
-// ascending within a gaussian.  Waves whose 64 gaussians are all invisible skip
-// the fields entirely (ballot).
+// The per-gaussian counts come from the projection kernel.  `scan_kernel`
+// (one workgroup) turns the per-block sums into exclusive block offsets and
+// the frame's pair total; `fill_kernel` re-runs the intersection of each
+// gaussian from the stored float32 fields (so it takes the count pass's exact
+// decisions), scans the counts inside the block with wave prefix sums, and
+// writes pairs (key, value = gaussian id) in gaussian-id order, macro-tiles
+// ascending within a gaussian.  Waves whose 64 gaussians are all invisible
+// skip the fields entirely (ballot).
 //
 // Key layout: (macro-tile << dbits) | (depth bits - dmin), where dmin and
 // dmin + 2^dbits - 1 bracket the float32 depth bits of the frame's visible
@@ -48,8 +46,56 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
   return v;
 }
 
-__device__ __forceinline__ uint64_t scan_word(uint32_t epoch, uint32_t flag, uint32_t count) {
-  return ((uint64_t)epoch << 34) | ((uint64_t)flag << 32) | (uint64_t)count;
+// One workgroup of 1024 threads: exclusive scan of the per-block (pairs,
+// visible) sums in place; writes the frame totals.
+constexpr int kScanThreads = 1024;
+__global__ void __launch_bounds__(kScanThreads)
+scan_kernel(uint32_t n_blocks, uint32_t* __restrict__ sums, uint32_t max_pairs,
+            DeviceCounters* __restrict__ dc) {
+  __shared__ uint32_t wave_tot[2][kScanThreads / 64];
+  const uint32_t per = (n_blocks + kScanThreads - 1) / kScanThreads;
+  const uint32_t b0 = threadIdx.x * per;
+  const uint32_t b1 = min(b0 + per, n_blocks);
+  uint32_t s_pairs = 0, s_vis = 0;
+  for (uint32_t b = b0; b < b1; ++b) {
+    s_pairs += sums[2 * b];
+    s_vis += sums[2 * b + 1];
+  }
+  const uint32_t ip = wave_incl_scan(s_pairs);
+  const uint32_t iv = wave_incl_scan(s_vis);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 63) {
+    wave_tot[0][wave] = ip;
+    wave_tot[1][wave] = iv;
+  }
+  __syncthreads();
+  uint32_t base_p = 0, base_v = 0;
+  for (int w = 0; w < wave; ++w) {
+    base_p += wave_tot[0][w];
+    base_v += wave_tot[1][w];
+  }
+  uint32_t run = base_p + ip - s_pairs;
+  for (uint32_t b = b0; b < b1; ++b) {
+    const uint32_t v = sums[2 * b];
+    sums[2 * b] = run;
+    run += v;
+  }
+  if (threadIdx.x == kScanThreads - 1) {
+    const uint32_t total = base_p + ip;
+    dc->n_pairs_total = total;
+    dc->n_pairs = total < max_pairs ? total : max_pairs;
+    dc->n_visible = base_v + iv;
+    if (total > max_pairs) dc->overflow |= HIGS_OVF_PAIRS;
+  }
+}
+
+hipError_t launch_scan(int64_t n, const uint32_t* cnt, uint32_t* block_sums, uint32_t max_pairs,
+                       DeviceCounters* dc, hipStream_t s) {
+  (void)cnt;
+  const uint32_t n_blocks = (uint32_t)((n + kProjBlock - 1) / kProjBlock);
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, s, n_blocks, block_sums,
+                     max_pairs, dc);
+  return hipGetLastError();
 }
 
 __global__ void __launch_bounds__(kProjBlock)
@@ -57,71 +103,21 @@ fill_kernel(int64_t n, CamArgs cam, const float* __restrict__ f_mx, const float*
             const float* __restrict__ f_a, const float* __restrict__ f_b,
             const float* __restrict__ f_c, const float* __restrict__ f_tau,
             const uint32_t* __restrict__ f_key, const uint32_t* __restrict__ f_cnt,
-            uint64_t* __restrict__ scan_status, uint32_t epoch, uint32_t max_pairs,
-            DeviceCounters* __restrict__ dc, uint64_t* __restrict__ keys,
+            const uint32_t* __restrict__ block_offsets, uint32_t max_pairs,
+            const DeviceCounters* __restrict__ dc, uint64_t* __restrict__ keys,
             uint32_t* __restrict__ vals) {
-  __shared__ uint32_t wave_tot[kProjBlock / 64], wave_vis[kProjBlock / 64];
-  __shared__ uint32_t s_bid, s_base;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (threadIdx.x == 0) s_bid = atomicAdd(&dc->fill_next, 1u);
-  __syncthreads();
-  const uint32_t bid = s_bid;
-  const uint32_t n_blocks = (uint32_t)((n + kProjBlock - 1) / kProjBlock);
-  const int64_t i = (int64_t)bid * kProjBlock + threadIdx.x;
+  __shared__ uint32_t wave_tot[kProjBlock / 64];
+  const int64_t i = (int64_t)blockIdx.x * kProjBlock + threadIdx.x;
   const uint32_t cnt = i < n ? f_cnt[i] : 0u;
   const uint32_t incl = wave_incl_scan(cnt);
-  const uint64_t vis = __ballot(cnt > 0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 63) wave_tot[wave] = incl;
-  if (lane == 0) wave_vis[wave] = (uint32_t)__popcll(vis);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t tot = 0, nvis = 0;
-    for (int w = 0; w < kProjBlock / 64; ++w) {
-      tot += wave_tot[w];
-      nvis += wave_vis[w];
-    }
-    if (nvis) atomicAdd(&dc->n_visible, nvis);
-    uint64_t* mine = scan_status + bid;
-    uint32_t prefix = 0;
-    if (bid == 0) {
-      __hip_atomic_store(mine, scan_word(epoch, kFlagPrefix, tot), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      __hip_atomic_store(mine, scan_word(epoch, kFlagAggregate, tot), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-      int64_t t = (int64_t)bid - 1;
-      uint32_t spins = 0;
-      while (t >= 0) {
-        const uint64_t w = __hip_atomic_load(scan_status + t, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t flag = (uint32_t)(w >> 32) & 3u;
-        if ((uint32_t)(w >> 34) != epoch || flag == 0) {  // not published yet
-          if (++spins > kMaxSpins) {  // cannot happen unless a block was lost
-            atomicOr(&dc->overflow, kErrSortStall);
-            break;
-          }
-          continue;
-        }
-        prefix += (uint32_t)w;
-        if (flag == kFlagPrefix) break;
-        --t;
-      }
-      __hip_atomic_store(mine, scan_word(epoch, kFlagPrefix, prefix + tot), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    }
-    s_base = prefix;
-    if (bid == n_blocks - 1) {
-      const uint32_t total = prefix + tot;
-      dc->n_pairs_total = total;
-      dc->n_pairs = total < max_pairs ? total : max_pairs;
-      if (total > max_pairs) atomicOr(&dc->overflow, (uint32_t)HIGS_OVF_PAIRS);
-    }
-  }
-  __syncthreads();
-  if (vis == 0) return;  // whole wave invisible
+  if (__ballot(cnt > 0) == 0) return;  // whole wave invisible
+  uint32_t base = block_offsets[2 * blockIdx.x];
+  for (int w = 0; w < wave; ++w) base += wave_tot[w];
   if (cnt == 0) return;
-  uint32_t at = s_base + incl - cnt;
-  for (int w = 0; w < wave; ++w) at += wave_tot[w];
+  uint32_t at = base + incl - cnt;
   BinFields f;
   f.mx = f_mx[i];
   f.my = f_my[i];
@@ -130,7 +126,7 @@ fill_kernel(int64_t n, CamArgs cam, const float* __restrict__ f_mx, const float*
   f.c = f_c[i];
   f.tau = f_tau[i];
   const uint32_t dmin = dc->key_min;
-  const uint32_t dbits = depth_bits(dc->key_min, dc->key_max);
+  const uint32_t dbits = depth_bits(dmin, dc->key_max);
   const uint64_t depth = (uint64_t)(f_key[i] - dmin);
   const uint32_t gid = (uint32_t)i;
   visit_macro_tiles(f, cam.width, cam.height, cam.n_mt_x, cam.n_mt_y, [&](uint32_t mt) {
@@ -144,13 +140,13 @@ fill_kernel(int64_t n, CamArgs cam, const float* __restrict__ f_mx, const float*
 
 hipError_t launch_fill(int64_t n, CamArgs cam, const float* f_mx, const float* f_my,
                        const float* f_a, const float* f_b, const float* f_c, const float* f_tau,
-                       const uint32_t* f_key, const uint32_t* f_cnt, uint64_t* scan_status,
-                       uint32_t epoch, uint32_t max_pairs, DeviceCounters* dc, uint64_t* keys,
+                       const uint32_t* f_key, const uint32_t* f_cnt, const uint32_t* block_offsets,
+                       uint32_t max_pairs, const DeviceCounters* dc, uint64_t* keys,
                        uint32_t* vals, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n + kProjBlock - 1) / kProjBlock);
   hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(kProjBlock), 0, s, n, cam, f_mx, f_my, f_a,
-                     f_b, f_c, f_tau, f_key, f_cnt, scan_status, epoch, max_pairs, dc, keys, vals);
+                     f_b, f_c, f_tau, f_key, f_cnt, block_offsets, max_pairs, dc, keys, vals);
   return hipGetLastError();
 }
 

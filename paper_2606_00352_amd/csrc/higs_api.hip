@@ -23,7 +23,7 @@ struct higs_ctx {
         *f_tau = nullptr;
   uint32_t *f_key = nullptr, *f_cnt = nullptr;
   RasterRecord* rec = nullptr;
-  uint64_t* scan_status = nullptr;  // emission look-back words, per block
+  uint32_t* block_sums = nullptr;  // per projection block: pair count, visible count
   uint64_t* keys[2] = {nullptr, nullptr};
   uint32_t* vals[2] = {nullptr, nullptr};
   uint64_t* dbg_keys = nullptr;
@@ -35,6 +35,12 @@ struct higs_ctx {
   uint32_t *mt_off = nullptr, *batch_first = nullptr, *batch_tab = nullptr, *active = nullptr;
   float4* partials = nullptr;
   DeviceCounters* dc = nullptr;
+  // adjoint buffers, allocated by the first higs_raster_backward
+  float2* bwd_state = nullptr;  // [max_batches][32 tiles][64 px]: T before, suffix X
+  float* dgeo = nullptr;        // [max_g][16] record gradients
+  // the scene arrays of the last higs_project (re-read by the adjoint)
+  const float *in_means = nullptr, *in_scales = nullptr, *in_quats = nullptr,
+              *in_opac = nullptr, *in_sh = nullptr;
 
   // frame state
   higs_camera cam{};
@@ -43,8 +49,7 @@ struct higs_ctx {
   int64_t n = 0;
   int stage = 0;  // 1 projected, 2 sorted, 3 batched, 4 rastered
   int n_mt = 0, n_passes = 0;
-  uint32_t epoch = 1;       // sort look-back epochs
-  uint32_t scan_epoch = 1;  // emission look-back epoch
+  uint32_t epoch = 1;  // sort look-back epochs
   hipStream_t last_stream = nullptr;
   int debug_flags = 0;
   // timing: events of the last `ring` frames, frame f in slot f % ring
@@ -95,9 +100,10 @@ void free_events(higs_ctx* c) {
 
 void free_all(higs_ctx* c) {
   void* bufs[] = {c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau, c->f_key, c->f_cnt,
-                  c->rec, c->scan_status, c->keys[0], c->keys[1], c->vals[0], c->vals[1],
+                  c->rec, c->block_sums, c->keys[0], c->keys[1], c->vals[0], c->vals[1],
                   c->dbg_keys, c->dbg_vals, c->hist, c->plan, c->status, c->mt_off,
-                  c->batch_first, c->batch_tab, c->active, c->partials, c->dc};
+                  c->batch_first, c->batch_tab, c->active, c->partials, c->dc,
+                  c->bwd_state, c->dgeo};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   free_events(c);
@@ -214,7 +220,7 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
   rc |= dalloc(&c->f_key, G);
   rc |= dalloc(&c->f_cnt, G);
   rc |= dalloc(&c->rec, G);
-  rc |= dalloc(&c->scan_status, nblk);
+  rc |= dalloc(&c->block_sums, 2 * nblk);
   rc |= dalloc(&c->keys[0], P);
   rc |= dalloc(&c->keys[1], P);
   rc |= dalloc(&c->vals[0], P);
@@ -235,7 +241,6 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
   }
   // look-back words start untagged (epoch 0 never matches a pass)
   if (hipMemset(c->status, 0, (size_t)c->max_tiles * kRadix * sizeof(uint64_t)) != hipSuccess ||
-      hipMemset(c->scan_status, 0, nblk * sizeof(uint64_t)) != hipSuccess ||
       hipMemset(c->dc, 0, sizeof(DeviceCounters)) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     free_all(c);
@@ -300,6 +305,11 @@ int higs_project(higs_ctx* c, int64_t n, const float* means, const float* scales
   c->stage = 0;
   if (c->timing()) c->frames += 1;
   c->cam = *cam;
+  c->in_means = means;
+  c->in_scales = scales;
+  c->in_quats = quats;
+  c->in_opac = opacities;
+  c->in_sh = sh;
   c->n = n;
   CamArgs& a = c->ca;
   a.width = cam->width;
@@ -329,7 +339,7 @@ int higs_project(higs_ctx* c, int64_t n, const float* means, const float* scales
     TimerScope ts(c, HIGS_TIMER_PROJECT, s);
     rc = hip_err(launch_project(n, means, scales, quats, opacities, sh, c->ca, c->pa, c->f_mx,
                                 c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau, c->f_key, c->f_cnt,
-                                c->rec, c->dc, s));
+                                c->rec, c->block_sums, c->dc, s));
   }
   if (rc) return rc;
   c->stage = 1;
@@ -344,15 +354,17 @@ int higs_bin_sort(higs_ctx* c, void* stream) {
   c->last_stream = s;
   int rc;
   {
-    TimerScope ts(c, HIGS_TIMER_SCAN, s);  // the scan is folded into the fill
+    TimerScope ts(c, HIGS_TIMER_SCAN, s);
+    rc = hip_err(launch_scan(c->n > 0 ? c->n : 0, c->f_cnt, c->block_sums,
+                             (uint32_t)c->max_pairs, c->dc, s));
   }
+  if (rc) return rc;
   {
     TimerScope ts(c, HIGS_TIMER_FILL, s);
     rc = hip_err(launch_fill(c->n, c->ca, c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau,
-                             c->f_key, c->f_cnt, c->scan_status, c->scan_epoch,
-                             (uint32_t)c->max_pairs, c->dc, c->keys[0], c->vals[0], s));
+                             c->f_key, c->f_cnt, c->block_sums, (uint32_t)c->max_pairs, c->dc,
+                             c->keys[0], c->vals[0], s));
   }
-  c->scan_epoch = c->scan_epoch + 1u >= (1u << 30) ? 1u : c->scan_epoch + 1u;
   if (rc) return rc;
   if ((c->debug_flags & HIGS_DEBUG_KEEP_PAIRS) && c->dbg_keys) {
     rc = hip_err(hipMemcpyAsync(c->dbg_keys, c->keys[0], (size_t)c->max_pairs * 8,
@@ -434,6 +446,32 @@ int higs_render(higs_ctx* c, int64_t n, const float* means, const float* scales,
   rc = higs_batch(c, stream);
   if (rc) return rc;
   return higs_raster(c, image, T_out, stream);
+}
+
+int higs_raster_backward(higs_ctx* c, const float* dL_dimage, const float* dL_dT, float* dmeans,
+                         float* dscales, float* dquats, float* dopacities, float* dsh,
+                         void* stream) {
+  if (!c || !dL_dimage) return HIGS_E_INVALID;
+  if (c->n > 0 && (!dmeans || !dscales || !dquats || !dopacities || !dsh)) return HIGS_E_INVALID;
+  if (c->stage < 4) return HIGS_E_STATE;
+  DeviceGuard g(c->device);
+  if (!c->bwd_state) {
+    if (dalloc(&c->bwd_state, (size_t)c->max_batches * kTilesPerMt * 64) != HIGS_OK ||
+        dalloc(&c->dgeo, (size_t)c->max_g * 16) != HIGS_OK) {
+      if (c->bwd_state) hipFree(c->bwd_state);
+      if (c->dgeo) hipFree(c->dgeo);
+      c->bwd_state = nullptr;
+      c->dgeo = nullptr;
+      return HIGS_E_NOMEM;
+    }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  c->last_stream = s;
+  const uint32_t* v2[2] = {c->vals[0], c->vals[1]};
+  return hip_err(launch_backward(c->n, c->in_means, c->in_scales, c->in_quats, c->in_sh, c->ca,
+                                 c->pa, v2, c->rec, c->f_cnt, c->batch_tab, c->batch_first,
+                                 c->active, c->partials, c->dc, dL_dimage, dL_dT, c->bwd_state,
+                                 c->dgeo, dmeans, dscales, dquats, dopacities, dsh, c->n_cus, s));
 }
 
 int higs_get_counts(higs_ctx* c, higs_counts* out) {

@@ -53,14 +53,15 @@ struct DeviceCounters {
   uint32_t raster_next;     // work counter of the persistent rasteriser
   uint32_t tile_next[kMaxPasses];  // work counters of the sort passes
   uint32_t sort_passes;     // radix passes that moved data (others skipped)
-  uint32_t fill_next;       // block counter of the emission kernel
+  uint32_t reserved0;
   unsigned long long n_evals;  // gaussian-tile evaluations (when counted)
   uint32_t key_min;         // smallest / largest float32 depth bits of the
   uint32_t key_max;         //   frame's visible gaussians (key compression)
-  uint32_t pad[10];
+  uint32_t bwd_next;        // work counter of the persistent raster adjoint
+  uint32_t pad[9];
 };
 
-// Look-back status words (emission scan and sort passes): 30-bit epoch,
+// Look-back status words (sort passes): 30-bit epoch,
 // 2-bit flag, 32-bit count.
 constexpr uint32_t kFlagAggregate = 1u;
 constexpr uint32_t kFlagPrefix = 2u;
@@ -98,12 +99,15 @@ hipError_t launch_project(int64_t n, const float* means, const float* scales, co
                           const float* opac, const float* sh, CamArgs cam, ParamArgs prm,
                           float* f_mx, float* f_my, float* f_a, float* f_b, float* f_c,
                           float* f_tau, uint32_t* f_key, uint32_t* f_cnt, RasterRecord* rec,
-                          DeviceCounters* dc, hipStream_t s);
+                          uint32_t* block_sums, DeviceCounters* dc, hipStream_t s);
+
+hipError_t launch_scan(int64_t n, const uint32_t* cnt, uint32_t* block_sums, uint32_t max_pairs,
+                       DeviceCounters* dc, hipStream_t s);
 
 hipError_t launch_fill(int64_t n, CamArgs cam, const float* f_mx, const float* f_my,
                        const float* f_a, const float* f_b, const float* f_c, const float* f_tau,
-                       const uint32_t* f_key, const uint32_t* f_cnt, uint64_t* scan_status,
-                       uint32_t epoch, uint32_t max_pairs, DeviceCounters* dc, uint64_t* keys,
+                       const uint32_t* f_key, const uint32_t* f_cnt, const uint32_t* block_offsets,
+                       uint32_t max_pairs, const DeviceCounters* dc, uint64_t* keys,
                        uint32_t* vals, hipStream_t s);
 
 struct SortBuffers {
@@ -130,6 +134,18 @@ hipError_t launch_raster(CamArgs cam, ParamArgs prm, const uint32_t* const* vals
 hipError_t launch_merge(CamArgs cam, ParamArgs prm, const uint32_t* batch_first,
                         const uint32_t* active, const float4* partials, const DeviceCounters* dc,
                         float* image, float* T_out, hipStream_t s);
+
+// Adjoint of the frame (clear, merge, raster and projection adjoints).
+// state: float2 per (batch, tile, pixel); dgeo: 16 floats per gaussian.
+hipError_t launch_backward(int64_t n, const float* means, const float* scales, const float* quats,
+                           const float* sh, CamArgs cam, ParamArgs prm,
+                           const uint32_t* const* vals2, const RasterRecord* rec,
+                           const uint32_t* f_cnt, const uint32_t* batch_tab,
+                           const uint32_t* batch_first, const uint32_t* active,
+                           const float4* partials, DeviceCounters* dc, const float* dimg,
+                           const float* dT, float2* state, float* dgeo, float* dmeans,
+                           float* dscales, float* dquats, float* dopac, float* dsh, int n_cus,
+                           hipStream_t s);
 
 int raster_workers_per_cu();
 

@@ -8,11 +8,12 @@
 // discrete decisions downstream (pair lists, depth order, batches) depend only
 // on these fields, so they can be reproduced bit for bit.  The SH colour runs
 // in float32.  The same thread counts the gaussian's macro-tile pairs
-// (predicate.h), and the block folds the depth bits of its visible gaussians
-// into the frame's [min, max] (used to compress the sort keys).
+// (predicate.h); the block writes the sums of its pair counts and visible
+// gaussians for the emission scan and folds the depth bits of its visible
+// gaussians into the frame's [min, max] (used to compress the sort keys).
 //
 // Outputs: SoA binning fields (coalesced), a 48-byte raster record per
-// visible gaussian, per-gaussian pair counts.
+// visible gaussian, per-gaussian pair counts and per-block count sums.
 #include "higs_internal.h"
 #include "predicate.h"
 
@@ -175,8 +176,10 @@ project_kernel(int64_t n, const float* __restrict__ means, const float* __restri
                float* __restrict__ f_mx, float* __restrict__ f_my, float* __restrict__ f_a,
                float* __restrict__ f_b, float* __restrict__ f_c, float* __restrict__ f_tau,
                uint32_t* __restrict__ f_key, uint32_t* __restrict__ f_cnt,
-               RasterRecord* __restrict__ rec, DeviceCounters* __restrict__ dc) {
+               RasterRecord* __restrict__ rec, uint32_t* __restrict__ block_sums,
+               DeviceCounters* __restrict__ dc) {
   __shared__ uint32_t wave_min[kProjBlock / 64], wave_max[kProjBlock / 64];
+  __shared__ uint32_t wave_sums[2][kProjBlock / 64];
   const int64_t i = (int64_t)blockIdx.x * kProjBlock + threadIdx.x;
   uint32_t cnt = 0;
   uint32_t kmin = 0xffffffffu, kmax = 0u;
@@ -239,27 +242,47 @@ project_kernel(int64_t n, const float* __restrict__ means, const float* __restri
     f_key[i] = key;
     f_cnt[i] = cnt;
   }
-  // frame-wide range of the visible depth bits
+  // block sums of the pair counts and visible gaussians (emission scan) and
+  // the frame-wide range of the visible depth bits
+  uint32_t s = cnt;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off, 64);
     kmin = min(kmin, (uint32_t)__shfl_xor(kmin, off, 64));
     kmax = max(kmax, (uint32_t)__shfl_xor(kmax, off, 64));
   }
+  const uint32_t vis = (uint32_t)__popcll(__ballot(cnt > 0));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) {
     wave_min[wave] = kmin;
     wave_max[wave] = kmax;
+    wave_sums[0][wave] = s;
+    wave_sums[1][wave] = vis;
   }
   __syncthreads();
+  if (threadIdx.x == 1) {
+    uint32_t tp = 0, tv = 0;
+#pragma unroll
+    for (int w = 0; w < kProjBlock / 64; ++w) {
+      tp += wave_sums[0][w];
+      tv += wave_sums[1][w];
+    }
+    block_sums[2 * blockIdx.x] = tp;
+    block_sums[2 * blockIdx.x + 1] = tv;
+  }
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int w = 1; w < kProjBlock / 64; ++w) {
       kmin = min(kmin, wave_min[w]);
       kmax = max(kmax, wave_max[w]);
     }
+    // only blocks that widen the range so far touch the shared words: with
+    // gaussians in random order that is a few dozen of them, not every block
     if (kmin <= kmax) {
-      atomicMin(&dc->key_min, kmin);
-      atomicMax(&dc->key_max, kmax);
+      if (kmin < __hip_atomic_load(&dc->key_min, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMin(&dc->key_min, kmin);
+      if (kmax > __hip_atomic_load(&dc->key_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(&dc->key_max, kmax);
     }
   }
 }
@@ -268,7 +291,7 @@ hipError_t launch_project(int64_t n, const float* means, const float* scales, co
                           const float* opac, const float* sh, CamArgs cam, ParamArgs prm,
                           float* f_mx, float* f_my, float* f_a, float* f_b, float* f_c,
                           float* f_tau, uint32_t* f_key, uint32_t* f_cnt, RasterRecord* rec,
-                          DeviceCounters* dc, hipStream_t s) {
+                          uint32_t* block_sums, DeviceCounters* dc, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   // camera centre, -R^T t, for the SH view direction
   float3 campos;
@@ -278,7 +301,7 @@ hipError_t launch_project(int64_t n, const float* means, const float* scales, co
   const unsigned blocks = (unsigned)((n + kProjBlock - 1) / kProjBlock);
   hipLaunchKernelGGL(project_kernel, dim3(blocks), dim3(kProjBlock), 0, s, n, means, scales,
                      quats, opac, sh, cam, prm, campos, f_mx, f_my,
-                     f_a, f_b, f_c, f_tau, f_key, f_cnt, rec, dc);
+                     f_a, f_b, f_c, f_tau, f_key, f_cnt, rec, block_sums, dc);
   return hipGetLastError();
 }
 

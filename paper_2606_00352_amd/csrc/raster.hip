@@ -22,66 +22,12 @@
 //   depth order, reads only active partials, accumulates
 //   C += T_acc C_b, T_acc *= T_b while T_acc >= t_eps and writes
 //   C + T_acc * background.
-#include "higs_internal.h"
+#include "raster_common.h"
 
 namespace higs {
 
 constexpr int kRasterThreads = 512;
 constexpr int kRasterWaves = kRasterThreads / 64;
-constexpr int kMiniBatches = kMaxBatch / 64;  // 16
-constexpr float kSqrtHalfLog2e = 0.8493218002880191f;  // sqrt(log2(e) / 2)
-constexpr float kAlphaMin = 1.0f / 255.0f;
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-struct RasterLds {
-  float4 ga[kMaxBatch];  // mx, my (macro-tile relative), l0', l1'
-  float4 gb[kMaxBatch];  // l2', o, r, g
-  float gc[kMaxBatch];   // b
-  uint64_t masks[kMiniBatches][kTilesPerMt];
-  uint32_t queue[kTilesPerMt];
-  uint32_t qcount;
-  uint32_t qnext;
-  uint32_t unit;
-};
-
-// Conservative test of one gaussian against the macro-tile's render tiles:
-// bit (r * 8 + c) is set when the ellipse {q <= tau'} (tau' slightly above
-// tau) reaches the pixel-centre rectangle of tile (c, r).  Per tile row the
-// ellipse's x-extent over the row's centre range uses the branches
-// x = (-l1 dy +- sqrt(tau' - (l2 dy)^2)) / l0 and their extremal points.
-__device__ __forceinline__ uint32_t tile_overlap(float mx, float my, float l0, float l1, float l2,
-                                                 float tau, int tiles_x, int tiles_y) {
-  const float taum = tau * 1.01f + 0.01f;
-  const float st = sqrtf(taum);
-  const float ry = st / l2;
-  const float s12 = sqrtf(l1 * l1 + l2 * l2);
-  const float dys = -l1 * st / (l2 * s12);
-  uint32_t mask = 0;
-  for (int r = 0; r < tiles_y; ++r) {
-    const float ya = (float)(r * kTile) + 0.5f - my;
-    const float yb = (float)(r * kTile) + 7.5f - my;
-    const float dlo = fmaxf(ya, -ry), dhi = fminf(yb, ry);
-    if (!(dlo <= dhi)) continue;
-    const float yp = fminf(fmaxf(dys, dlo), dhi);
-    const float ym = fminf(fmaxf(-dys, dlo), dhi);
-    const float sp = sqrtf(fmaxf(0.0f, taum - (l2 * yp) * (l2 * yp)));
-    const float sm = sqrtf(fmaxf(0.0f, taum - (l2 * ym) * (l2 * ym)));
-    const float xp = mx + (sp - l1 * yp) / l0 + 0.5f;
-    const float xm = mx - (sm + l1 * ym) / l0 - 0.5f;
-    // tile c spans pixel centres [8c + 0.5, 8c + 7.5]
-    const float flo = fminf(fmaxf(ceilf((xm - 7.5f) * 0.125f), 0.0f), 8.0f);
-    const float fhi = fminf(fmaxf(floorf((xp - 0.5f) * 0.125f), -1.0f), (float)(tiles_x - 1));
-    const int clo = (int)flo, chi = (int)fhi;
-    if (clo <= chi) mask |= ((0xffu >> (7 - (chi - clo))) << clo) << (r * 8);
-  }
-  return mask;
-}
-
-__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
 
 template <bool kCountEvals>
 __global__ void __launch_bounds__(kRasterThreads)
@@ -104,86 +50,33 @@ raster_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ vals0,
     __syncthreads();
     const uint32_t u = L.unit;
     if (u >= n_units) break;
-    const uint32_t mt = batch_tab[3 * u + 0];
-    const uint32_t start = batch_tab[3 * u + 1];
-    const int len = (int)batch_tab[3 * u + 2];
-    const int mtx = (int)(mt % (uint32_t)cam.n_mt_x), mty = (int)(mt / (uint32_t)cam.n_mt_x);
-    const int x0 = mtx * kMtW, y0 = mty * kMtH;
-    const int tiles_x = min(kMtTilesX, (cam.width - x0 + kTile - 1) / kTile);
-    const int tiles_y = min(kMtTilesY, (cam.height - y0 + kTile - 1) / kTile);
-    const int K = (len + 63) >> 6;
-
-    // Phase 1: load + inline visibility + transpose
-    for (int k = wave; k < K; k += kRasterWaves) {
-      const int j = k * 64 + lane;
-      uint32_t tmask = 0;
-      if (j < len) {
-        const uint32_t gid = sorted[start + j];
-        const float4* rp = reinterpret_cast<const float4*>(rec + gid);
-        const float4 A = rp[0], B = rp[1], C = rp[2];
-        const float mxr = A.x - (float)x0, myr = A.y - (float)y0;
-        L.ga[j] = make_float4(mxr, myr, A.z * kSqrtHalfLog2e, A.w * kSqrtHalfLog2e);
-        L.gb[j] = make_float4(B.x * kSqrtHalfLog2e, B.y, B.z, B.w);
-        L.gc[j] = C.x;
-        tmask = tile_overlap(mxr, myr, A.z, A.w, B.x, C.y, tiles_x, tiles_y);
-      }
-      uint64_t mine = 0;
-#pragma unroll
-      for (int t = 0; t < kTilesPerMt; ++t) {
-        const uint64_t b = __ballot((tmask >> t) & 1u);
-        if (lane == t) mine = b;
-      }
-      if (lane < kTilesPerMt) L.masks[k][lane] = mine;
-    }
-    __syncthreads();
-
-    // work queue of active tiles
-    if (wave == 0) {
-      uint64_t hit = 0;
-      if (lane < kTilesPerMt)
-        for (int k = 0; k < K; ++k) hit |= L.masks[k][lane];
-      const uint64_t act = __ballot(lane < kTilesPerMt && hit != 0);
-      if (lane < kTilesPerMt && hit != 0)
-        L.queue[__popcll(act & ((1ull << lane) - 1ull))] = (uint32_t)lane;
-      if (lane == 0) {
-        L.qcount = (uint32_t)__popcll(act);
-        active[u] = (uint32_t)act;
-      }
-    }
-    __syncthreads();
+    const UnitInfo I = unit_info(cam, batch_tab, u);
+    const uint32_t act = stage_unit<kRasterWaves>(L, I, sorted, rec, lane, wave);
+    if (tid == 0) active[u] = act;
 
     // Phase 2: waves claim tiles
-    const uint32_t qcount = L.qcount;
     for (;;) {
-      uint32_t qi = 0;
-      if (lane == 0) qi = atomicAdd(&L.qnext, 1u);
-      qi = __builtin_amdgcn_readfirstlane(qi);
-      if (qi >= qcount) break;
-      const int t = (int)L.queue[qi];
+      const int t = next_tile(L, lane);
+      if (t < 0) break;
       const float pxr = (float)((t & 7) * kTile) + pxo;
       const float pyr = (float)((t >> 3) * kTile) + pyo;
       float cr = 0.0f, cg = 0.0f, cb = 0.0f, T = 1.0f;
       uint32_t evals = 0;
-      for (int k = 0; k < K; ++k) {
+      for (int k = 0; k < I.K; ++k) {
         uint64_t m = uniform64(L.masks[k][t]);
         if (kCountEvals) evals += (uint32_t)__popcll(m);
         while (m) {
           const int j = __ffsll((unsigned long long)m) - 1;
           m &= m - 1ull;
           const int gi = k * 64 + j;
-          const float4 A = L.ga[gi];
           const float4 B = L.gb[gi];
-          const float bb = L.gc[gi];
-          const float dx = pxr - A.x, dy = pyr - A.y;
-          const float uu = A.z * dx + A.w * dy;
-          const float vv = B.x * dy;
-          const float q = uu * uu + vv * vv;
-          const float al = fminf(amax, B.y * __builtin_amdgcn_exp2f(-q));
+          const PixelEval ev = eval_alpha(L.ga[gi], B, pxr, pyr, amax);
+          const float al = ev.al;
           if (T >= eps && al >= kAlphaMin) {
             const float w = al * T;
             cr += w * B.z;
             cg += w * B.w;
-            cb += w * bb;
+            cb += w * L.gc[gi];
             T = T * (1.0f - al);
           }
         }

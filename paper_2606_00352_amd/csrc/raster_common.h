@@ -1,0 +1,162 @@
+// Pieces shared by the forward rasteriser and its adjoint: the LDS image of
+// one (macro-tile, batch) processing unit, the conservative gaussian-tile
+// test, the staging of a unit (records gathered into LDS, per-tile gaussian
+// masks by ballot transpose, queue of active tiles) and the per-pixel alpha,
+// so that both kernels evaluate exactly the same float32 expression.
+#pragma once
+#include "higs_internal.h"
+
+namespace higs {
+
+constexpr int kMiniBatches = kMaxBatch / 64;  // 16
+constexpr float kSqrtHalfLog2e = 0.8493218002880191f;  // sqrt(log2(e) / 2)
+constexpr float kAlphaMin = 1.0f / 255.0f;
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+struct RasterLds {
+  float4 ga[kMaxBatch];  // mx, my (macro-tile relative), l0', l1'
+  float4 gb[kMaxBatch];  // l2', o, r, g
+  float gc[kMaxBatch];   // b
+  uint64_t masks[kMiniBatches][kTilesPerMt];
+  uint32_t queue[kTilesPerMt];
+  uint32_t qcount;
+  uint32_t qnext;
+  uint32_t unit;
+};
+
+// Conservative test of one gaussian against the macro-tile's render tiles:
+// bit (r * 8 + c) is set when the ellipse {q <= tau'} (tau' slightly above
+// tau) reaches the pixel-centre rectangle of tile (c, r).  Per tile row the
+// ellipse's x-extent over the row's centre range uses the branches
+// x = (-l1 dy +- sqrt(tau' - (l2 dy)^2)) / l0 and their extremal points.
+__device__ __forceinline__ uint32_t tile_overlap(float mx, float my, float l0, float l1, float l2,
+                                                 float tau, int tiles_x, int tiles_y) {
+  const float taum = tau * 1.01f + 0.01f;
+  const float st = sqrtf(taum);
+  const float ry = st / l2;
+  const float s12 = sqrtf(l1 * l1 + l2 * l2);
+  const float dys = -l1 * st / (l2 * s12);
+  uint32_t mask = 0;
+  for (int r = 0; r < tiles_y; ++r) {
+    const float ya = (float)(r * kTile) + 0.5f - my;
+    const float yb = (float)(r * kTile) + 7.5f - my;
+    const float dlo = fmaxf(ya, -ry), dhi = fminf(yb, ry);
+    if (!(dlo <= dhi)) continue;
+    const float yp = fminf(fmaxf(dys, dlo), dhi);
+    const float ym = fminf(fmaxf(-dys, dlo), dhi);
+    const float sp = sqrtf(fmaxf(0.0f, taum - (l2 * yp) * (l2 * yp)));
+    const float sm = sqrtf(fmaxf(0.0f, taum - (l2 * ym) * (l2 * ym)));
+    const float xp = mx + (sp - l1 * yp) / l0 + 0.5f;
+    const float xm = mx - (sm + l1 * ym) / l0 - 0.5f;
+    // tile c spans pixel centres [8c + 0.5, 8c + 7.5]
+    const float flo = fminf(fmaxf(ceilf((xm - 7.5f) * 0.125f), 0.0f), 8.0f);
+    const float fhi = fminf(fmaxf(floorf((xp - 0.5f) * 0.125f), -1.0f), (float)(tiles_x - 1));
+    const int clo = (int)flo, chi = (int)fhi;
+    if (clo <= chi) mask |= ((0xffu >> (7 - (chi - clo))) << clo) << (r * 8);
+  }
+  return mask;
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// alpha = min(alpha_max, o exp(-q/2)) at the pixel centre (pxr, pyr)
+// relative to the macro-tile, from the prescaled factors in LDS:
+// q' = (l0' dx + l1' dy)^2 + (l2' dy)^2 = q log2(e)/2, exp(-q/2) = exp2(-q').
+struct PixelEval {
+  float dx, dy, u, v, e, al;
+};
+__device__ __forceinline__ PixelEval eval_alpha(const float4& A, const float4& B, float pxr,
+                                                float pyr, float amax) {
+  PixelEval r;
+  r.dx = pxr - A.x;
+  r.dy = pyr - A.y;
+  r.u = A.z * r.dx + A.w * r.dy;
+  r.v = B.x * r.dy;
+  const float q = r.u * r.u + r.v * r.v;
+  r.e = __builtin_amdgcn_exp2f(-q);
+  r.al = fminf(amax, B.y * r.e);
+  return r;
+}
+
+struct UnitInfo {
+  uint32_t mt, start;
+  int len, K, x0, y0, tiles_x, tiles_y;
+};
+
+__device__ __forceinline__ UnitInfo unit_info(const CamArgs& cam, const uint32_t* batch_tab,
+                                              uint32_t u) {
+  UnitInfo I;
+  I.mt = batch_tab[3 * u + 0];
+  I.start = batch_tab[3 * u + 1];
+  I.len = (int)batch_tab[3 * u + 2];
+  const int mtx = (int)(I.mt % (uint32_t)cam.n_mt_x), mty = (int)(I.mt / (uint32_t)cam.n_mt_x);
+  I.x0 = mtx * kMtW;
+  I.y0 = mty * kMtH;
+  I.tiles_x = min(kMtTilesX, (cam.width - I.x0 + kTile - 1) / kTile);
+  I.tiles_y = min(kMtTilesY, (cam.height - I.y0 + kTile - 1) / kTile);
+  I.K = (I.len + 63) >> 6;
+  return I;
+}
+
+// Phase 1 of a unit, by all waves of the workgroup: wave w takes mini-batches
+// k = w, w + n_waves, ... (64 gaussians, one per lane), gathers the 48-byte
+// records by sorted id into LDS (macro-tile-relative, factors prescaled),
+// tests each gaussian against the render tiles and transposes the 32-bit
+// per-gaussian tile masks into 64-bit per-tile gaussian masks with 32
+// ballots.  Then wave 0 builds the queue of tiles with any gaussian and
+// returns their mask (in lane 0 of wave 0).  Ends with a barrier.
+template <int kWavesPerGroup>
+__device__ __forceinline__ uint32_t stage_unit(RasterLds& L, const UnitInfo& I,
+                                               const uint32_t* __restrict__ sorted,
+                                               const RasterRecord* __restrict__ rec, int lane,
+                                               int wave) {
+  for (int k = wave; k < I.K; k += kWavesPerGroup) {
+    const int j = k * 64 + lane;
+    uint32_t tmask = 0;
+    if (j < I.len) {
+      const uint32_t gid = sorted[I.start + j];
+      const float4* rp = reinterpret_cast<const float4*>(rec + gid);
+      const float4 A = rp[0], B = rp[1], C = rp[2];
+      const float mxr = A.x - (float)I.x0, myr = A.y - (float)I.y0;
+      L.ga[j] = make_float4(mxr, myr, A.z * kSqrtHalfLog2e, A.w * kSqrtHalfLog2e);
+      L.gb[j] = make_float4(B.x * kSqrtHalfLog2e, B.y, B.z, B.w);
+      L.gc[j] = C.x;
+      tmask = tile_overlap(mxr, myr, A.z, A.w, B.x, C.y, I.tiles_x, I.tiles_y);
+    }
+    uint64_t mine = 0;
+#pragma unroll
+    for (int t = 0; t < kTilesPerMt; ++t) {
+      const uint64_t b = __ballot((tmask >> t) & 1u);
+      if (lane == t) mine = b;
+    }
+    if (lane < kTilesPerMt) L.masks[k][lane] = mine;
+  }
+  __syncthreads();
+  uint32_t act32 = 0;
+  if (wave == 0) {
+    uint64_t hit = 0;
+    if (lane < kTilesPerMt)
+      for (int k = 0; k < I.K; ++k) hit |= L.masks[k][lane];
+    const uint64_t act = __ballot(lane < kTilesPerMt && hit != 0);
+    if (lane < kTilesPerMt && hit != 0)
+      L.queue[__popcll(act & ((1ull << lane) - 1ull))] = (uint32_t)lane;
+    if (lane == 0) L.qcount = (uint32_t)__popcll(act);
+    act32 = (uint32_t)act;
+  }
+  __syncthreads();
+  return act32;
+}
+
+// Next tile of the unit's queue for this wave (uniform), or -1.
+__device__ __forceinline__ int next_tile(RasterLds& L, int lane) {
+  uint32_t qi = 0;
+  if (lane == 0) qi = atomicAdd(&L.qnext, 1u);
+  qi = __builtin_amdgcn_readfirstlane(qi);
+  return qi < L.qcount ? (int)L.queue[qi] : -1;
+}
+
+}  // namespace higs

@@ -25,7 +25,7 @@ TIMER_NAMES = ("project", "scan", "fill", "sort", "batch", "raster", "merge")
 EXPORTS = ("higs_default_params", "higs_ctx_create", "higs_ctx_destroy", "higs_project",
            "higs_bin_sort", "higs_batch", "higs_raster", "higs_render", "higs_get_counts",
            "higs_set_debug", "higs_debug_copy", "higs_set_timing", "higs_get_timers",
-           "higs_error_string")
+           "higs_error_string", "higs_raster_backward")
 
 
 class HigsError(RuntimeError):
@@ -82,6 +82,7 @@ def lib():
             "higs_set_timing": (ctypes.c_int, [P, ctypes.c_int]),
             "higs_get_timers": (ctypes.c_int, [P, P]),
             "higs_error_string": (ctypes.c_char_p, [ctypes.c_int]),
+            "higs_raster_backward": (ctypes.c_int, [P, P, P, P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -158,6 +159,7 @@ class Context:
         self._h = h
         self.n = 0
         self.n_mt = 0
+        self.frame_id = 0  # advances with every projected frame
 
     def close(self):
         if getattr(self, "_h", None):
@@ -173,6 +175,7 @@ class Context:
     # ---- stages ----------------------------------------------------------------
     def project(self, means, scales, quats, opacities, sh, cam, stream=None):
         n = int(means.shape[0])
+        self.frame_id += 1
         self._cam = camera_c(cam)
         self.n = n
         self.n_mt = ((cam.width + 63) // 64) * ((cam.height + 31) // 32)
@@ -190,12 +193,21 @@ class Context:
 
     def render(self, means, scales, quats, opacities, sh, cam, image, T=None, stream=None):
         n = int(means.shape[0])
+        self.frame_id += 1
         self._cam = camera_c(cam)
         self.n = n
         self.n_mt = ((cam.width + 63) // 64) * ((cam.height + 31) // 32)
         _check(lib().higs_render(self._h, n, _ptr(means), _ptr(scales), _ptr(quats), _ptr(opacities),
                                  _ptr(sh), ctypes.byref(self._cam), _ptr(image), _ptr(T), _stream(stream)),
                "higs_render")
+
+    def raster_backward(self, d_image, d_T, d_means, d_scales, d_quats, d_opacities, d_sh, stream=None):
+        """Adjoint of the last frame (higs_raster_backward): writes the gradient
+        tensors d_means [n,3], d_scales [n,3], d_quats [n,4], d_opacities [n],
+        d_sh [n,(deg+1)^2,3] from d_image [H,W,3] and d_T [H,W] (or None)."""
+        _check(lib().higs_raster_backward(self._h, _ptr(d_image), _ptr(d_T), _ptr(d_means), _ptr(d_scales),
+                                          _ptr(d_quats), _ptr(d_opacities), _ptr(d_sh), _stream(stream)),
+               "higs_raster_backward")
 
     # ---- host read-back ----------------------------------------------------------
     def counts(self) -> Counts:
@@ -283,3 +295,60 @@ def render(ctx: Context, tensors, cam, with_T: bool = True, stream=None):
     T = torch.empty((cam.height, cam.width), dtype=torch.float32, device=dev) if with_T else None
     ctx.render(*tensors, cam, image, T, stream)
     return image, T
+
+
+def _render_function():
+    import torch
+
+    class RenderFunction(torch.autograd.Function):
+        """Differentiable frame: forward = higs_render, backward =
+        higs_raster_backward.  The context must not render another frame
+        between the two (checked)."""
+
+        @staticmethod
+        def forward(fctx, means, scales, quats, opacities, sh, hctx, cam):
+            tens = tuple(t.contiguous() for t in (means, scales, quats, opacities, sh))
+            image, T = render(hctx, tens, cam)
+            fctx.hctx = hctx
+            fctx.frame_id = hctx.frame_id
+            fctx.save_for_backward(*tens)
+            return image, T
+
+        @staticmethod
+        def backward(fctx, d_image, d_T):
+            hctx = fctx.hctx
+            if hctx.frame_id != fctx.frame_id:
+                raise RuntimeError("the context rendered another frame after this one: "
+                                   "its backward needs the frame's intermediates")
+            tens = fctx.saved_tensors
+            outs = [torch.empty_like(t) for t in tens]
+            if d_image is None:
+                cam = hctx._cam
+                d_image = torch.zeros((cam.height, cam.width, 3), device=tens[0].device)
+            d_image = d_image.contiguous().float()
+            d_T = None if d_T is None else d_T.contiguous().float()
+            hctx.raster_backward(d_image, d_T, *outs)
+            return (*outs, None, None)
+
+    return RenderFunction
+
+
+_RENDER_FN = None
+
+
+def render_differentiable(hctx: Context, means, scales, quats, opacities, sh, cam):
+    """(image [H,W,3], T [H,W]) with gradients to every scene tensor (scales
+    linear, opacities in [0, 1], as higs_project takes them)."""
+    global _RENDER_FN
+    if _RENDER_FN is None:
+        _RENDER_FN = _render_function()
+    return _RENDER_FN.apply(means, scales, quats, opacities, sh, hctx, cam)
+
+
+def render_trainable(hctx: Context, means, log_scales, quats, opacity_logits, sh, cam):
+    """The training parameterisation: scales = exp(log_scales), opacities =
+    sigmoid(opacity_logits), applied in torch; gradients reach the raw
+    parameters through torch's own chain rule."""
+    import torch
+    return render_differentiable(hctx, means, torch.exp(log_scales), quats, torch.sigmoid(opacity_logits),
+                                 sh, cam)
