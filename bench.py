@@ -45,16 +45,29 @@ COPY_CALIBRATION_BYTES = 1 << 30
 # SHA-256 of the kernel's source file at the time the counters were taken: if
 # the source differs, the figure no longer describes the kernel and is
 # reported as null.
-MEASURED_TRAFFIC = {}
-KERNEL_SOURCES = {"project": "project.hip", "fill": "emit.hip", "sort": "sort.hip",
-                  "raster": "raster.hip"}
+MEASURED_TRAFFIC = {
+    # profiles/frame_1080p_5p8m_hbm_traffic.md (sort: histogram + plan + every
+    # onesweep dispatch of a frame)
+    "raster": {"src_sha256": "6b4cefc39c36eefeab63a8777b0b4b6d6685ad5e175c8331064551d7265da7cb",
+               "bytes_per_launch": 1514105296},
+    "project": {"src_sha256": "955e069c36980c85778133b8d10294be94c4776d6b03d9a92ebd8efd3f90dcf4",
+                "bytes_per_launch": 1825441097},
+    "fill": {"src_sha256": "609e8597d94764ce66659993a8b308d9a6673c2051060c74109ad27851925f2e",
+             "bytes_per_launch": 284277598},
+    "sort": {"src_sha256": "afcf793b04b47a4e06b4cd00fe913615a7262a828752a740094afbbefcd25b59",
+             "bytes_per_launch": 1232807136},
+}
+KERNEL_SOURCES = {"project": ("project.hip", "predicate.h"), "fill": ("emit.hip", "predicate.h"),
+                  "sort": ("sort.hip",), "raster": ("raster.hip", "raster_common.h")}
 
 
 def kernel_source_sha(kernel):
     import hashlib
-    path = os.path.join(ROOT, "paper_2606_00352_amd", "csrc", KERNEL_SOURCES[kernel])
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2606_00352_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel):
