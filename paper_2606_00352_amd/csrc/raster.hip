@@ -69,16 +69,17 @@ raster_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ vals0,
           const int j = __ffsll((unsigned long long)m) - 1;
           m &= m - 1ull;
           const int gi = k * 64 + j;
+          const float4 A = L.ga[gi];
           const float4 B = L.gb[gi];
-          const PixelEval ev = eval_alpha(L.ga[gi], B, pxr, pyr, amax);
-          const float al = ev.al;
-          if (T >= eps && al >= kAlphaMin) {
-            const float w = al * T;
-            cr += w * B.z;
-            cg += w * B.w;
-            cb += w * L.gc[gi];
-            T = T * (1.0f - al);
-          }
+          const float bb = L.gc[gi];
+          const float al = eval_alpha(A, B, pxr, pyr, amax).al;
+          // branchless blend: a skipped gaussian adds w = 0 and keeps T exactly
+          const float a = (T >= eps && al >= kAlphaMin) ? al : 0.0f;
+          const float w = a * T;
+          cr += w * B.z;
+          cg += w * B.w;
+          cb += w * bb;
+          T = T * (1.0f - a);
         }
         if (__ballot(T >= eps) == 0) break;
       }
