@@ -146,6 +146,86 @@ def backward_leg(n=1_000_000, warmup=5, steps=20):
     return res
 
 
+def serving_leg(warm=1.0, measured=4.0, drain=6.0, rate=2000.0, budget_gb=96.0, max_in_flight=16):
+    """The serving workload: four resident clustered scenes (0.5M, 1.5M, 3M,
+    5.8M gaussians), Poisson requests at `rate`/s for warm + measured seconds,
+    each a random orbit camera at 720p, 1080p or 4K.  Requests are replayed in
+    real time against the server (continuous batching, max_in_flight frames at
+    once) and against the plain renderer (the same server with one frame at a
+    time), each allowed `drain` seconds after the last arrival.  Latency =
+    completion seen by the host - arrival; served frames/s = completions
+    within the measured window / its length; percentiles over the requests
+    that arrived in the measured window (unfinished ones are counted)."""
+    import collections
+    import numpy as np
+    import torch
+    from paper_2606_00352_amd import higs, scenes
+    t = time.perf_counter()
+    sc = scenes.serving_scenes()
+    tens = [higs.scene_tensors(x, "cuda:0") for x in sc]
+    nmax = max(x.n for x in sc)
+    del sc
+    trace = scenes.serving_trace(warm + measured, rate)
+    log(f"serving: scenes ready in {time.perf_counter() - t:.1f} s, {len(trace)} requests")
+    res = scenes.SERVING_RESOLUTIONS
+    classes = [(w, h, int(k * nmax)) for (w, h), k in zip(res, (1.5, 2.5, 4.5))]
+
+    def run(mif):
+        srv = higs.Server(classes, max_gaussians=nmax, hbm_budget=int(budget_gb * 2**30), max_in_flight=mif)
+        for k, tt in enumerate(tens):
+            srv.add_scene(k, tt)
+        pool = {c: [torch.empty((h, w, 3), device="cuda:0") for _ in range(2 * mif)]
+                for c, (w, h) in enumerate(res)}
+        holding, lat, done_at, gpu_ms = {}, {}, {}, []
+        pending = collections.deque()
+        overflow = 0
+        nxt = 0
+        t0 = time.perf_counter()
+        end = trace[-1].arrival + drain
+        while len(lat) < len(trace):
+            now = time.perf_counter() - t0
+            if now > end:
+                break
+            while nxt < len(trace) and trace[nxt].arrival <= now:
+                pending.append(trace[nxt])
+                nxt += 1
+            kept = collections.deque()
+            while pending:
+                r = pending.popleft()
+                if pool[r.cls]:
+                    buf = pool[r.cls].pop()
+                    holding[r.id] = (r.cls, buf)
+                    srv.submit(r.id, r.scene, r.cls, r.camera, buf)
+                else:
+                    kept.append(r)
+            pending = kept
+            for rid, ms, ovf, cls in srv.poll():
+                tdone = time.perf_counter() - t0
+                lat[rid] = tdone - trace[rid].arrival
+                done_at[rid] = tdone
+                gpu_ms.append(ms)
+                overflow += ovf != 0
+                c, buf = holding.pop(rid)
+                pool[c].append(buf)
+        torch.cuda.synchronize()
+        st = srv.stats()
+        srv.close()
+        in_win = [r.id for r in trace if r.arrival >= warm]
+        served = sum(1 for d in done_at.values() if warm <= d < warm + measured) / measured
+        l = np.array([lat.get(i, np.inf) for i in in_win])
+        return {"served_fps": round(served, 1), "completed": len(lat), "requests": len(trace),
+                "unfinished_in_window": int(np.isinf(l).sum()),
+                "p50_ms": round(float(np.percentile(l, 50)) * 1e3, 2),
+                "p99_ms": round(float(np.percentile(l, 99)) * 1e3, 2) if np.isfinite(np.percentile(l, 99)) else None,
+                "mean_gpu_ms": round(float(np.mean(gpu_ms)), 4), "overflow_frames": overflow,
+                "contexts": st.contexts, "context_gb": round(st.bytes / 2**30, 2)}
+
+    out = {"workload": f"4 resident scenes (0.5M/1.5M/3M/5.8M), Poisson {rate:.0f} req/s, 720p/1080p/4K, "
+                       f"{warm:.0f} s warm-up + {measured:.0f} s measured",
+           "mixed": run(max_in_flight), "plain": run(1), "max_in_flight": max_in_flight}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +234,7 @@ def main():
     ap.add_argument("--gaussians", type=int, default=5_800_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the frame path is single-GPU; --gpus must be 1", file=sys.stderr)
@@ -275,6 +356,10 @@ def main():
         del ctx
         result["backward"] = backward_leg()
         log(f"backward: {result['backward']}")
+    if not args.no_serving:
+        log("serving leg")
+        result["serving"] = serving_leg()
+        log(f"serving: {result['serving']}")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(scene, cams[0])

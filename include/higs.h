@@ -17,6 +17,8 @@
  *                   macro-tile (sec. 3.4, Algorithms 1 and 2) and the
  *                   post-blend merge of the batch partials with Eq. 1.
  *   higs_render   - all of the above in one call.
+ *   higs_server_* - a render server: resident scenes, continuous batching of
+ *                   frame requests over contexts and streams (serving).
  *   higs_raster_backward - the adjoint of the last frame: gradients of a loss
  *                   on the image (and final transmittance) with respect to
  *                   the gaussian parameters (the backward that the paper's
@@ -123,6 +125,13 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
 /* Releases the context and its device memory (synchronises its stream). */
 int higs_ctx_destroy(higs_ctx* ctx);
 
+/* Device memory (bytes) a context created with these capacities allocates
+ * (host-only arithmetic, no device call; negative HIGS_E_INVALID for
+ * non-positive sizes).  The adjoint buffers of higs_raster_backward come on
+ * top (max_batches * 16 KiB + max_gaussians * 64 B). */
+int64_t higs_ctx_footprint(const higs_params* params, int64_t max_gaussians, int64_t max_pairs,
+                           int64_t max_batches, int32_t max_width, int32_t max_height);
+
 /* Stage 1: projects n gaussians for `cam` (sec. 4.2).  Inputs (device):
  *   means [n,3], scales [n,3] (linear), quats [n,4] as (w,x,y,z), any norm,
  *   opacities [n] (in [0,1]), sh [n, (sh_degree+1)^2, 3].
@@ -185,6 +194,63 @@ int higs_render(higs_ctx* ctx, int64_t n, const float* means, const float* scale
 int higs_raster_backward(higs_ctx* ctx, const float* dL_dimage, const float* dL_dT,
                          float* dmeans, float* dscales, float* dquats, float* dopacities,
                          float* dsh, void* stream);
+
+/* ---- Serving ---------------------------------------------------------------
+ * A render server keeps several scenes resident on the device and renders a
+ * stream of requests (scene, camera, resolution class) with continuous
+ * batching: a request is admitted as soon as a frame context of its resolution
+ * class is idle, or a new one fits the server's HBM budget (idle contexts of
+ * other classes are released to make room, least recently used first; each
+ * context's size is higs_ctx_footprint of its class capacities).  Every
+ * context renders on a HIP stream of its own, so admitted frames overlap on
+ * the device.  The server is driven from one host thread: higs_server_submit
+ * queues, higs_server_poll retires finished frames and admits queued ones;
+ * neither blocks (releasing a context for the budget synchronises the device).
+ * A request's image is the same rendered alone or in the mix.  The paper
+ * renders single frames; this is the serving loop around its frame path. */
+typedef struct higs_server higs_server;
+
+#define HIGS_MAX_CLASSES 4
+typedef struct {
+  int32_t n_classes;                     /* resolution classes, 1..HIGS_MAX_CLASSES */
+  int32_t width[HIGS_MAX_CLASSES];       /* largest image of each class */
+  int32_t height[HIGS_MAX_CLASSES];
+  int64_t max_pairs[HIGS_MAX_CLASSES];   /* pair capacity of a context of the class */
+  int64_t max_gaussians;                 /* the largest scene */
+  int64_t hbm_budget;                    /* bytes of frame contexts the server may hold */
+  int32_t max_in_flight;                 /* frames rendering at once (1: the plain
+                                            one-frame-at-a-time renderer) */
+} higs_server_config;
+
+typedef struct {
+  int64_t request_id;
+  float gpu_ms;       /* device time of the frame, events on its stream */
+  uint32_t overflow;  /* HIGS_OVF_* bits of the frame (its image is then undefined) */
+  int32_t cls;
+} higs_completion;
+
+typedef struct {
+  int32_t queued, in_flight, contexts;
+  int64_t bytes;      /* device memory held by frame contexts */
+  int64_t completed, evictions;
+} higs_server_stats;
+
+/* params: NULL for the defaults; the scene arrays of higs_server_add_scene are
+ * device pointers owned by the caller that must stay valid and unchanged while
+ * the server renders them.  image of higs_server_submit: device [H, W, 3] of
+ * the camera's size (at most the class size, else HIGS_E_CAPACITY), written
+ * when the request completes.  higs_server_poll returns the number of
+ * completions written to done (<= max_done), or a negative error. */
+int higs_server_create(int device, const higs_params* params, const higs_server_config* cfg,
+                       higs_server** out);
+int higs_server_destroy(higs_server* server);
+int higs_server_add_scene(higs_server* server, int32_t scene_id, int64_t n, const float* means,
+                          const float* scales, const float* quats, const float* opacities,
+                          const float* sh);
+int higs_server_submit(higs_server* server, int64_t request_id, int32_t scene_id, int32_t cls,
+                       const higs_camera* cam, float* image);
+int higs_server_poll(higs_server* server, higs_completion* done, int32_t max_done);
+int higs_server_get_stats(higs_server* server, higs_server_stats* out);
 
 /* Synchronises the stream of the last call and reports the frame's sizes. */
 int higs_get_counts(higs_ctx* ctx, higs_counts* out);

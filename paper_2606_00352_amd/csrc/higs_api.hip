@@ -210,6 +210,7 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
   const size_t G = (size_t)max_gaussians, P = (size_t)max_pairs, B = (size_t)max_batches;
   const size_t nblk = (G + kProjBlock - 1) / kProjBlock;
   c->max_tiles = (uint32_t)((P + kSortTile - 1) / kSortTile);
+  // (the sizes below are the ones higs_ctx_footprint adds up)
   int rc = HIGS_OK;
   rc |= dalloc(&c->f_mx, G);
   rc |= dalloc(&c->f_my, G);
@@ -239,16 +240,46 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
     delete c;
     return HIGS_E_NOMEM;
   }
-  // look-back words start untagged (epoch 0 never matches a pass)
-  if (hipMemset(c->status, 0, (size_t)c->max_tiles * kRadix * sizeof(uint64_t)) != hipSuccess ||
-      hipMemset(c->dc, 0, sizeof(DeviceCounters)) != hipSuccess ||
-      hipDeviceSynchronize() != hipSuccess) {
+  // look-back words start untagged (epoch 0 never matches a pass); cleared on
+  // a stream of the context's own, so that creating a context does not wait for
+  // work in flight on other streams
+  hipStream_t init = nullptr;
+  bool ok = hipStreamCreateWithFlags(&init, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipMemsetAsync(c->status, 0, (size_t)c->max_tiles * kRadix * sizeof(uint64_t),
+                            init) == hipSuccess;
+  ok = ok && hipMemsetAsync(c->dc, 0, sizeof(DeviceCounters), init) == hipSuccess;
+  ok = ok && hipStreamSynchronize(init) == hipSuccess;
+  if (init) (void)hipStreamDestroy(init);
+  if (!ok) {
     free_all(c);
     delete c;
     return HIGS_E_HIP;
   }
   *out = c;
   return HIGS_OK;
+}
+
+int64_t higs_ctx_footprint(const higs_params* params, int64_t max_gaussians, int64_t max_pairs,
+                           int64_t max_batches, int32_t max_width, int32_t max_height) {
+  (void)params;
+  if (max_gaussians < 1 || max_pairs < 1 || max_batches < 1 || max_width < 1 || max_height < 1)
+    return HIGS_E_INVALID;
+  const int64_t G = max_gaussians, P = max_pairs, B = max_batches;
+  const int64_t nblk = (G + kProjBlock - 1) / kProjBlock;
+  const int64_t tiles = (P + kSortTile - 1) / kSortTile;
+  const int64_t mt = (int64_t)((max_width + kMtW - 1) / kMtW) * ((max_height + kMtH - 1) / kMtH);
+  int64_t bytes = 0;
+  bytes += G * (6 * 4 + 2 * 4);                // binning fields, key, count
+  bytes += G * (int64_t)sizeof(RasterRecord);  // raster records
+  bytes += 2 * nblk * 4;                       // per-block sums
+  bytes += P * (2 * 8 + 2 * 4);                // two key and two value buffers
+  bytes += (int64_t)kMaxPasses * kRadix * 4 + ((int64_t)kMaxPasses + kMaxPasses * kRadix) * 4;
+  bytes += tiles * kRadix * 8;                 // sort look-back words
+  bytes += 2 * (mt + 1) * 4;                   // macro-tile offsets, first batches
+  bytes += B * (3 * 4 + 4);                    // batch table, active masks
+  bytes += B * kTilesPerMt * 64 * (int64_t)sizeof(float4);  // partials
+  bytes += (int64_t)sizeof(DeviceCounters);
+  return bytes;
 }
 
 int higs_ctx_destroy(higs_ctx* c) {
@@ -458,8 +489,8 @@ int higs_raster_backward(higs_ctx* c, const float* dL_dimage, const float* dL_dT
   if (!c->bwd_state) {
     if (dalloc(&c->bwd_state, (size_t)c->max_batches * kTilesPerMt * 64) != HIGS_OK ||
         dalloc(&c->dgeo, (size_t)c->max_g * 16) != HIGS_OK) {
-      if (c->bwd_state) hipFree(c->bwd_state);
-      if (c->dgeo) hipFree(c->dgeo);
+      if (c->bwd_state) (void)hipFree(c->bwd_state);
+      if (c->dgeo) (void)hipFree(c->dgeo);
       c->bwd_state = nullptr;
       c->dgeo = nullptr;
       return HIGS_E_NOMEM;
@@ -587,3 +618,10 @@ int higs_get_timers(higs_ctx* c, float ms[HIGS_NUM_TIMERS]) {
 }
 
 }  // extern "C"
+
+namespace higs {
+int ctx_enqueue_counters(higs_ctx* c, void* pinned_dst, hipStream_t s) {
+  if (!c || !pinned_dst) return HIGS_E_INVALID;
+  return hip_err(hipMemcpyAsync(pinned_dst, c->dc, sizeof(DeviceCounters), hipMemcpyDeviceToHost, s));
+}
+}  // namespace higs

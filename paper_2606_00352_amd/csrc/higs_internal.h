@@ -149,4 +149,8 @@ hipError_t launch_backward(int64_t n, const float* means, const float* scales, c
 
 int raster_workers_per_cu();
 
+// Enqueues a copy of the context's frame counters into pinned host memory
+// (sizeof(DeviceCounters) bytes) on stream s.
+int ctx_enqueue_counters(higs_ctx* c, void* pinned_dst, hipStream_t s);
+
 }  // namespace higs

@@ -25,7 +25,9 @@ TIMER_NAMES = ("project", "scan", "fill", "sort", "batch", "raster", "merge")
 EXPORTS = ("higs_default_params", "higs_ctx_create", "higs_ctx_destroy", "higs_project",
            "higs_bin_sort", "higs_batch", "higs_raster", "higs_render", "higs_get_counts",
            "higs_set_debug", "higs_debug_copy", "higs_set_timing", "higs_get_timers",
-           "higs_error_string", "higs_raster_backward")
+           "higs_error_string", "higs_raster_backward", "higs_ctx_footprint",
+           "higs_server_create", "higs_server_destroy", "higs_server_add_scene", "higs_server_submit",
+           "higs_server_poll", "higs_server_get_stats")
 
 
 class HigsError(RuntimeError):
@@ -56,6 +58,26 @@ class Counts(ctypes.Structure):
                 ("n_evaluations", ctypes.c_int64)]
 
 
+MAX_CLASSES = 4
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("n_classes", ctypes.c_int32), ("width", ctypes.c_int32 * MAX_CLASSES),
+                ("height", ctypes.c_int32 * MAX_CLASSES), ("max_pairs", ctypes.c_int64 * MAX_CLASSES),
+                ("max_gaussians", ctypes.c_int64), ("hbm_budget", ctypes.c_int64),
+                ("max_in_flight", ctypes.c_int32)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("request_id", ctypes.c_int64), ("gpu_ms", ctypes.c_float),
+                ("overflow", ctypes.c_uint32), ("cls", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int32), ("in_flight", ctypes.c_int32), ("contexts", ctypes.c_int32),
+                ("bytes", ctypes.c_int64), ("completed", ctypes.c_int64), ("evictions", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -83,6 +105,13 @@ def lib():
             "higs_get_timers": (ctypes.c_int, [P, P]),
             "higs_error_string": (ctypes.c_char_p, [ctypes.c_int]),
             "higs_raster_backward": (ctypes.c_int, [P, P, P, P, P, P, P, P, P]),
+            "higs_ctx_footprint": (i64, [P, i64, i64, i64, i32, i32]),
+            "higs_server_create": (ctypes.c_int, [ctypes.c_int, P, P, P]),
+            "higs_server_destroy": (ctypes.c_int, [P]),
+            "higs_server_add_scene": (ctypes.c_int, [P, i32, i64, P, P, P, P, P]),
+            "higs_server_submit": (ctypes.c_int, [P, i64, i32, i32, P, P]),
+            "higs_server_poll": (ctypes.c_int, [P, P, i32]),
+            "higs_server_get_stats": (ctypes.c_int, [P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -279,6 +308,72 @@ class Context:
         if first != 0:
             raise ValueError("partials are read from the first batch")
         return self._copy(DBG_PARTIALS, np.zeros((count, 32, 64, 4), np.float32))
+
+
+def ctx_footprint(max_gaussians: int, max_pairs: int, max_batches: int, max_width: int, max_height: int,
+                  **params) -> int:
+    """Device bytes a context with these capacities allocates (host-only)."""
+    p = default_params(**params)
+    return int(lib().higs_ctx_footprint(ctypes.byref(p), int(max_gaussians), int(max_pairs), int(max_batches),
+                                        int(max_width), int(max_height)))
+
+
+class Server:
+    """higs_server: resident scenes, continuous batching of frame requests over
+    contexts (one stream each) within an HBM budget.  classes: [(W, H,
+    max_pairs), ...]."""
+
+    def __init__(self, classes, max_gaussians: int, hbm_budget: int, max_in_flight: int = 16, device: int = 0,
+                 **params):
+        cfg = ServerConfig()
+        cfg.n_classes = len(classes)
+        for k, (w, h, mp) in enumerate(classes):
+            cfg.width[k], cfg.height[k], cfg.max_pairs[k] = int(w), int(h), int(mp)
+        cfg.max_gaussians = int(max_gaussians)
+        cfg.hbm_budget = int(hbm_budget)
+        cfg.max_in_flight = int(max_in_flight)
+        self.params = default_params(**params)
+        h = ctypes.c_void_p()
+        _check(lib().higs_server_create(device, ctypes.byref(self.params), ctypes.byref(cfg), ctypes.byref(h)),
+               "higs_server_create")
+        self._h = h
+        self._keep = []          # scene tensors stay referenced while the server lives
+        self._done = (Completion * 256)()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().higs_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_scene(self, scene_id: int, tensors):
+        means, scales, quats, opac, sh = tensors
+        self._keep.append(tensors)
+        _check(lib().higs_server_add_scene(self._h, int(scene_id), int(means.shape[0]), _ptr(means), _ptr(scales),
+                                           _ptr(quats), _ptr(opac), _ptr(sh)), "higs_server_add_scene")
+
+    def submit(self, request_id: int, scene_id: int, cls: int, cam, image):
+        c = camera_c(cam)
+        _check(lib().higs_server_submit(self._h, int(request_id), int(scene_id), int(cls), ctypes.byref(c),
+                                        _ptr(image)), "higs_server_submit")
+
+    def poll(self):
+        """Retires finished frames and admits queued ones; returns a list of
+        (request_id, gpu_ms, overflow, cls)."""
+        n = lib().higs_server_poll(self._h, self._done, len(self._done))
+        if n < 0:
+            raise HigsError(n, "higs_server_poll")
+        return [(d.request_id, d.gpu_ms, d.overflow, d.cls) for d in self._done[:n]]
+
+    def stats(self) -> ServerStats:
+        st = ServerStats()
+        _check(lib().higs_server_get_stats(self._h, ctypes.byref(st)), "higs_server_get_stats")
+        return st
 
 
 def scene_tensors(scene, device="cuda"):

@@ -185,3 +185,47 @@ def config2(n: int = 6_000_000, n_views: int = 60):
     """6M clustered gaussians with larger splats, 3840x2160, f = 2200."""
     scene = clustered_scene(n, seed=2, log_scale_mean=math.log(0.05), log_scale_std=0.7)
     return scene, orbit_cameras(n_views, 102, 3840, 2160, 2200.0)
+
+
+# Serving workload ---------------------------------------------------------------
+
+SERVING_SIZES = (500_000, 1_500_000, 3_000_000, 5_800_000)
+SERVING_RESOLUTIONS = ((1280, 720), (1920, 1080), (3840, 2160))
+
+
+def serving_scenes(sizes=SERVING_SIZES, first_seed: int = 31):
+    """Resident scenes of the serving workload: clustered scenes (the 1080p
+    benchmark generator) of the given sizes, seeds first_seed, first_seed + 1, ..."""
+    return [clustered_scene(n, seed=first_seed + k) for k, n in enumerate(sizes)]
+
+
+@dataclasses.dataclass
+class Request:
+    id: int
+    arrival: float      # seconds from the start of the trace
+    scene: int          # index into the resident scenes
+    cls: int            # index into the resolutions
+    camera: Camera
+
+
+def serving_trace(duration: float, rate: float = 2000.0, seed: int = 35, n_scenes: int = 4,
+                  resolutions=SERVING_RESOLUTIONS, radius: float = 25.0):
+    """Poisson arrivals at `rate` per second over `duration` seconds; each
+    request picks a scene and a resolution uniformly and an orbit camera with
+    azimuth ~ U(0, 2 pi), elevation ~ U(10, 30) degrees at `radius`, focal
+    length 1100 * W / 1920 (the 1080p field of view at every size)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        scene = int(rng.integers(n_scenes))
+        cls = int(rng.integers(len(resolutions)))
+        th = rng.uniform(0.0, 2.0 * math.pi)
+        e = math.radians(rng.uniform(10.0, 30.0))
+        w, h = resolutions[cls]
+        eye = (radius * math.cos(e) * math.sin(th), -radius * math.sin(e), -radius * math.cos(e) * math.cos(th))
+        out.append(Request(len(out), t, scene, cls, look_at_origin(eye, w, h, 1100.0 * w / 1920.0)))
+    return out

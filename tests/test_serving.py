@@ -1,0 +1,133 @@
+"""The render server (higs_server_*): continuous batching of frame requests
+over contexts and streams within an HBM budget.
+
+CPU: the context footprint the admission budget is counted in (host-only
+arithmetic) against the sizes of the arrays a context holds; the request
+trace generator.  GPU: every request's image in a mixed burst (several
+scenes and resolutions, frames overlapping on the device) equals the image
+rendered alone on a fresh context, bit for bit; so does the plain
+one-frame-at-a-time mode; a budget too small for all classes at once still
+serves every request, by releasing idle contexts."""
+import numpy as np
+import pytest
+
+from paper_2606_00352_amd import higs, scenes
+
+
+def test_context_footprint_counts_every_array():
+    G, P, B, W, H = 1000, 5000, 40, 200, 100
+    n_mt = ((W + 63) // 64) * ((H + 31) // 32)
+    nblk = (G + 255) // 256
+    tiles = (P + 4095) // 4096
+    want = (G * (8 * 4 + 48) + 2 * nblk * 4 + P * 24 + 8 * 256 * 4 + (8 + 8 * 256) * 4 + tiles * 256 * 8
+            + 2 * (n_mt + 1) * 4 + B * 16 + B * 32 * 64 * 16)
+    got = higs.ctx_footprint(G, P, B, W, H)
+    assert 0 < got - want <= 512          # plus the frame counters
+    assert higs.ctx_footprint(G, 2 * P, B, W, H) > got
+    assert higs.ctx_footprint(G, P, 2 * B, W, H) - got == B * (16 + 32 * 64 * 16)
+    assert higs.ctx_footprint(0, P, B, W, H) == higs.E_INVALID
+
+
+def test_serving_trace_is_poisson_and_uniform():
+    tr = scenes.serving_trace(5.0, rate=2000.0)
+    gaps = np.diff([r.arrival for r in tr])
+    assert abs(len(tr) / 5.0 - 2000.0) < 2000.0 * 0.05
+    assert abs(gaps.mean() - 1 / 2000.0) < 0.05 / 2000.0
+    assert abs(np.std(gaps) / gaps.mean() - 1.0) < 0.05    # exponential: cv = 1
+    counts = np.bincount([r.cls for r in tr], minlength=3)
+    assert counts.min() > 0.3 * len(tr) and counts.max() < 0.37 * len(tr)
+    assert {r.camera.width for r in tr} == {1280, 1920, 3840}
+    assert np.array_equal(np.bincount([r.scene for r in tr]) > 0.2 * len(tr), [True] * 4)
+
+
+SMALL = ((160, 96), (320, 180), (640, 360))
+
+
+def _burst(n_req, seed=3):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for k in range(n_req):
+        cls = int(rng.integers(3))
+        w, h = SMALL[cls]
+        th, e = rng.uniform(0, 2 * np.pi), np.radians(rng.uniform(10, 30))
+        eye = (25 * np.cos(e) * np.sin(th), -25 * np.sin(e), -25 * np.cos(e) * np.cos(th))
+        reqs.append((k, int(rng.integers(3)), cls, scenes.look_at_origin(eye, w, h, 1100.0 * w / 1920.0)))
+    return reqs
+
+
+def _serve(tens, reqs, budget, max_in_flight, max_g):
+    import torch
+    srv = higs.Server([(w, h, 4 * max_g) for w, h in SMALL], max_gaussians=max_g, hbm_budget=budget,
+                      max_in_flight=max_in_flight)
+    for k, t in enumerate(tens):
+        srv.add_scene(k, t)
+    images = {}
+    for rid, sc, cls, cam in reqs:
+        images[rid] = torch.full((cam.height, cam.width, 3), -1.0, device="cuda")
+        srv.submit(rid, sc, cls, cam, images[rid])
+    done = {}
+    for _ in range(200000):
+        for rid, ms, ovf, cls in srv.poll():
+            done[rid] = (ms, ovf)
+        if len(done) == len(reqs):
+            break
+    st = srv.stats()
+    srv.close()
+    return images, done, st
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("max_in_flight", [6, 1])
+def test_alone_equals_in_mix(max_in_flight):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sc = [scenes.clustered_scene(n, seed=50 + k, n_clusters=12) for k, n in enumerate((20_000, 40_000, 80_000))]
+    tens = [higs.scene_tensors(s) for s in sc]
+    reqs = _burst(36)
+    images, done, st = _serve(tens, reqs, budget=1 << 40, max_in_flight=max_in_flight, max_g=80_000)
+    assert len(done) == len(reqs) and all(ovf == 0 for _, ovf in done.values())
+    assert all(ms > 0 for ms, _ in done.values())
+    assert st.queued == 0 and st.in_flight == 0 and st.completed == len(reqs)
+    ctx = higs.Context(80_000, 640, 360, max_pairs=4 * 80_000)
+    for rid, s, cls, cam in reqs:
+        alone, _ = higs.render(ctx, tens[s], cam, with_T=False)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, images[rid]), rid
+
+
+@pytest.mark.gpu
+def test_small_budget_releases_idle_contexts():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sc = [scenes.clustered_scene(n, seed=60 + k, n_clusters=12) for k, n in enumerate((10_000, 30_000, 50_000))]
+    tens = [higs.scene_tensors(s) for s in sc]
+    reqs = _burst(24, seed=9)
+    biggest = max(higs.ctx_footprint(50_000, 4 * 50_000, 4 * 50_000 // 1024 + ((w + 63) // 64) * ((h + 31) // 32) + 16,
+                                     w, h) for w, h in SMALL)
+    images, done, st = _serve(tens, reqs, budget=int(biggest * 1.5), max_in_flight=4, max_g=50_000)
+    assert len(done) == len(reqs)
+    assert st.evictions > 0 and st.contexts <= 2 and st.bytes <= int(biggest * 1.5)
+    ctx = higs.Context(50_000, 640, 360, max_pairs=4 * 50_000)
+    for rid, s, cls, cam in reqs:
+        alone, _ = higs.render(ctx, tens[s], cam, with_T=False)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, images[rid]), rid
+
+
+@pytest.mark.gpu
+def test_submit_checks_the_class_size():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    srv = higs.Server([(64, 64, 1000)], max_gaussians=100, hbm_budget=1 << 30, max_in_flight=1)
+    t = higs.scene_tensors(scenes.uniform_scene(100, seed=1))
+    srv.add_scene(0, t)
+    img = torch.empty((80, 80, 3), device="cuda")
+    with pytest.raises(higs.HigsError) as e:
+        srv.submit(0, 0, 0, scenes.camera_at_origin(80, 80, 80.0), img)
+    assert e.value.code == higs.E_CAPACITY
+    with pytest.raises(higs.HigsError):
+        srv.submit(1, 7, 0, scenes.camera_at_origin(64, 64, 64.0), img)   # unknown scene
+    srv.close()
