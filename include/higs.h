@@ -84,7 +84,15 @@ typedef struct {
   float t_eps;        /* compositing stops once T < t_eps (1e-4) */
   float near_z;       /* cull at camera-space depth <= near_z (0.2) */
   float dilation;     /* added to the 2D covariance diagonal (0.3) */
+  int32_t sort_mode;  /* HIGS_SORT_ONESWEEP (default) or HIGS_SORT_SEGMENTED */
 } higs_params;
+
+/* How pairs are binned and depth-ordered; both give the same (macro-tile,
+ * depth, id) order.  SEGMENTED: binning straight into per-macro-tile segments
+ * and an independent sort of each (sec. 3.2-3.3, 4.3-4.4); ONESWEEP: a global
+ * LSD radix sort of composite (macro-tile, depth) keys. */
+#define HIGS_SORT_SEGMENTED 0
+#define HIGS_SORT_ONESWEEP 1
 
 /* Pinhole camera, OpenCV axes (x right, y down, z forward).  Pixel (i, j)
  * has its centre at (i + 0.5, j + 0.5).  HOST memory. */
@@ -290,7 +298,8 @@ int higs_debug_copy(higs_ctx* ctx, int which, void* host_dst, size_t bytes);
  * any host synchronisation; higs_get_timers synchronises and writes the mean
  * over those frames, ms[HIGS_TIMER_*] in milliseconds. */
 #define HIGS_TIMER_PROJECT 0 /* projection + SH + per-gaussian pair counts */
-#define HIGS_TIMER_SCAN 1    /* exclusive scan of the per-block pair counts */
+#define HIGS_TIMER_SCAN 1    /* pair counts and their scan (segmented: per-macro-tile
+                                counts and segment offsets) */
 #define HIGS_TIMER_FILL 2    /* pair emission */
 #define HIGS_TIMER_SORT 3    /* all radix-sort kernels */
 #define HIGS_TIMER_BATCH 4   /* macro-tile offsets + batch table */

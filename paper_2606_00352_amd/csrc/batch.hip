@@ -99,4 +99,12 @@ hipError_t launch_batch(int n_mt, uint32_t batch_cap, uint32_t max_batches, cons
   return hipGetLastError();
 }
 
+hipError_t launch_batch_from_offsets(int n_mt, uint32_t batch_cap, uint32_t max_batches,
+                                     DeviceCounters* dc, const uint32_t* mt_off,
+                                     uint32_t* batch_first, uint32_t* batch_tab, hipStream_t s) {
+  hipLaunchKernelGGL(batch_table_kernel, dim3(1), dim3(kBtThreads), 0, s, n_mt, batch_cap,
+                     max_batches, mt_off, dc, batch_first, batch_tab);
+  return hipGetLastError();
+}
+
 }  // namespace higs

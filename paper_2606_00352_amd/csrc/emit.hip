@@ -21,17 +21,20 @@
 
 namespace higs {
 
-__global__ void clear_kernel(DeviceCounters* dc, uint32_t* hist, int n_hist) {
+__global__ void clear_kernel(DeviceCounters* dc, uint32_t* hist, int n_hist, uint32_t* seg_count,
+                             int n_seg) {
   uint32_t* w = reinterpret_cast<uint32_t*>(dc);
   const int nw = (int)(sizeof(DeviceCounters) / 4);
   for (int k = threadIdx.x; k < nw; k += blockDim.x) w[k] = 0;
   for (int k = threadIdx.x; k < n_hist; k += blockDim.x) hist[k] = 0;
+  for (int k = threadIdx.x; k < n_seg; k += blockDim.x) seg_count[k] = 0;
   __syncthreads();
   if (threadIdx.x == 0) dc->key_min = 0xffffffffu;
 }
 
-hipError_t launch_clear(DeviceCounters* dc, uint32_t* hist, int n_hist, hipStream_t s) {
-  hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(256), 0, s, dc, hist, n_hist);
+hipError_t launch_clear(DeviceCounters* dc, uint32_t* hist, int n_hist, uint32_t* seg_count,
+                        int n_seg, hipStream_t s) {
+  hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(1024), 0, s, dc, hist, n_hist, seg_count, n_seg);
   return hipGetLastError();
 }
 

@@ -8,6 +8,9 @@
 
 #include <new>
 
+#include <cstring>
+#include <vector>
+
 #include "higs_internal.h"
 
 using namespace higs;
@@ -35,6 +38,10 @@ struct higs_ctx {
   uint32_t *mt_off = nullptr, *batch_first = nullptr, *batch_tab = nullptr, *active = nullptr;
   float4* partials = nullptr;
   DeviceCounters* dc = nullptr;
+  // segmented sort: per macro-tile counts, fill cursors, chunk and block tables
+  uint32_t *seg_count = nullptr, *seg_cursor = nullptr, *seg_chunk_off = nullptr,
+           *seg_blk_off = nullptr;
+  bool segmented() const { return params.sort_mode == HIGS_SORT_SEGMENTED; }
   // adjoint buffers, allocated by the first higs_raster_backward
   float2* bwd_state = nullptr;  // [max_batches][32 tiles][64 px]: T before, suffix X
   float* dgeo = nullptr;        // [max_g][16] record gradients
@@ -103,7 +110,8 @@ void free_all(higs_ctx* c) {
                   c->rec, c->block_sums, c->keys[0], c->keys[1], c->vals[0], c->vals[1],
                   c->dbg_keys, c->dbg_vals, c->hist, c->plan, c->status, c->mt_off,
                   c->batch_first, c->batch_tab, c->active, c->partials, c->dc,
-                  c->bwd_state, c->dgeo};
+                  c->bwd_state, c->dgeo, c->seg_count, c->seg_cursor, c->seg_chunk_off,
+                  c->seg_blk_off};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   free_events(c);
@@ -153,6 +161,7 @@ void higs_default_params(higs_params* p) {
   p->t_eps = 1e-4f;
   p->near_z = 0.2f;
   p->dilation = 0.3f;
+  p->sort_mode = HIGS_SORT_ONESWEEP;
 }
 
 const char* higs_error_string(int code) {
@@ -179,6 +188,10 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
   if (p.tile_px != kTile || p.mt_tiles_x != kMtTilesX || p.mt_tiles_y != kMtTilesY)
     return HIGS_E_UNSUPPORTED;
   if (p.sh_degree < 0 || p.sh_degree > 3) return HIGS_E_UNSUPPORTED;
+  if (p.sort_mode != HIGS_SORT_SEGMENTED && p.sort_mode != HIGS_SORT_ONESWEEP) return HIGS_E_INVALID;
+  if (p.sort_mode == HIGS_SORT_SEGMENTED &&
+      ((int64_t)((max_width + kMtW - 1) / kMtW) * ((max_height + kMtH - 1) / kMtH) > kSegMaxMt))
+    return HIGS_E_UNSUPPORTED;
   if (p.batch_cap < 1 || p.batch_cap > kMaxBatch) return HIGS_E_INVALID;
   if (!(p.alpha_max > 0.0f && p.alpha_max <= 1.0f) || !(p.t_eps >= 0.0f) ||
       !(p.dilation >= 0.0f) || !(p.near_z == p.near_z))
@@ -235,6 +248,10 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
   rc |= dalloc(&c->active, B);
   rc |= dalloc(&c->partials, B * kTilesPerMt * 64);
   rc |= dalloc(&c->dc, 1);
+  rc |= dalloc(&c->seg_count, (size_t)c->max_mt);
+  rc |= dalloc(&c->seg_cursor, (size_t)c->max_mt);
+  rc |= dalloc(&c->seg_chunk_off, (size_t)c->max_mt + 1);
+  rc |= dalloc(&c->seg_blk_off, (size_t)c->max_mt + 1);
   if (rc != HIGS_OK) {
     free_all(c);
     delete c;
@@ -364,7 +381,8 @@ int higs_project(higs_ctx* c, int64_t n, const float* means, const float* scales
   c->pa.sh_degree = c->params.sh_degree;
   c->n_mt = a.n_mt_x * a.n_mt_y;
   c->n_passes = (32 + n_bits((uint32_t)(c->n_mt - 1)) + kRadixBits - 1) / kRadixBits;
-  int rc = hip_err(launch_clear(c->dc, c->hist, kMaxPasses * kRadix, s));
+  int rc = hip_err(launch_clear(c->dc, c->hist, kMaxPasses * kRadix, c->seg_count,
+                                c->segmented() ? c->n_mt : 0, s));
   if (rc) return rc;
   {
     TimerScope ts(c, HIGS_TIMER_PROJECT, s);
@@ -377,6 +395,31 @@ int higs_project(higs_ctx* c, int64_t n, const float* means, const float* scales
   return HIGS_OK;
 }
 
+namespace {
+SegBuffers seg_buffers(higs_ctx* c) {
+  SegBuffers sb;
+  sb.seg_count = c->seg_count;
+  sb.cursor = c->seg_cursor;
+  sb.mt_off = c->mt_off;
+  sb.chunk_off = c->seg_chunk_off;
+  sb.blk_off = c->seg_blk_off;
+  sb.comp = c->keys[0];
+  sb.runs = c->keys[1];
+  sb.ids = c->vals[0];
+  return sb;
+}
+
+int keep_pairs(higs_ctx* c, hipStream_t s) {
+  if (!(c->debug_flags & HIGS_DEBUG_KEEP_PAIRS) || !c->dbg_keys) return HIGS_OK;
+  int rc = hip_err(hipMemcpyAsync(c->dbg_keys, c->keys[0], (size_t)c->max_pairs * 8,
+                                  hipMemcpyDeviceToDevice, s));
+  if (!rc && !c->segmented())
+    rc = hip_err(hipMemcpyAsync(c->dbg_vals, c->vals[0], (size_t)c->max_pairs * 4,
+                                hipMemcpyDeviceToDevice, s));
+  return rc;
+}
+}  // namespace
+
 int higs_bin_sort(higs_ctx* c, void* stream) {
   if (!c) return HIGS_E_INVALID;
   if (c->stage < 1) return HIGS_E_STATE;
@@ -384,6 +427,31 @@ int higs_bin_sort(higs_ctx* c, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
   int rc;
+  if (c->segmented()) {
+    const SegBuffers sb = seg_buffers(c);
+    {
+      TimerScope ts(c, HIGS_TIMER_SCAN, s);
+      rc = hip_err(launch_seg_count(c->n, c->ca, c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c,
+                                    c->f_tau, c->f_cnt, sb, (uint32_t)c->max_pairs, c->dc, s));
+    }
+    if (rc) return rc;
+    {
+      TimerScope ts(c, HIGS_TIMER_FILL, s);
+      rc = hip_err(launch_seg_fill(c->n, c->ca, c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c,
+                                   c->f_tau, c->f_key, c->f_cnt, sb, (uint32_t)c->max_pairs,
+                                   c->dc, s));
+    }
+    if (rc) return rc;
+    rc = keep_pairs(c, s);
+    if (rc) return rc;
+    {
+      TimerScope ts(c, HIGS_TIMER_SORT, s);
+      rc = hip_err(launch_seg_sort(c->n, c->n_mt, sb, (uint32_t)c->max_pairs, c->dc, c->n_cus, s));
+    }
+    if (rc) return rc;
+    c->stage = 2;
+    return HIGS_OK;
+  }
   {
     TimerScope ts(c, HIGS_TIMER_SCAN, s);
     rc = hip_err(launch_scan(c->n > 0 ? c->n : 0, c->f_cnt, c->block_sums,
@@ -397,13 +465,8 @@ int higs_bin_sort(higs_ctx* c, void* stream) {
                              c->keys[0], c->vals[0], s));
   }
   if (rc) return rc;
-  if ((c->debug_flags & HIGS_DEBUG_KEEP_PAIRS) && c->dbg_keys) {
-    rc = hip_err(hipMemcpyAsync(c->dbg_keys, c->keys[0], (size_t)c->max_pairs * 8,
-                                hipMemcpyDeviceToDevice, s));
-    if (!rc) rc = hip_err(hipMemcpyAsync(c->dbg_vals, c->vals[0], (size_t)c->max_pairs * 4,
-                                         hipMemcpyDeviceToDevice, s));
-    if (rc) return rc;
-  }
+  rc = keep_pairs(c, s);
+  if (rc) return rc;
   SortBuffers sb;
   sb.keys[0] = c->keys[0];
   sb.keys[1] = c->keys[1];
@@ -434,8 +497,13 @@ int higs_batch(higs_ctx* c, void* stream) {
   int rc;
   {
     TimerScope ts(c, HIGS_TIMER_BATCH, s);
-    rc = hip_err(launch_batch(c->n_mt, (uint32_t)c->params.batch_cap, (uint32_t)c->max_batches, k2,
-                              c->dc, c->mt_off, c->batch_first, c->batch_tab, s));
+    if (c->segmented())
+      rc = hip_err(launch_batch_from_offsets(c->n_mt, (uint32_t)c->params.batch_cap,
+                                             (uint32_t)c->max_batches, c->dc, c->mt_off,
+                                             c->batch_first, c->batch_tab, s));
+    else
+      rc = hip_err(launch_batch(c->n_mt, (uint32_t)c->params.batch_cap, (uint32_t)c->max_batches,
+                                k2, c->dc, c->mt_off, c->batch_first, c->batch_tab, s));
   }
   if (rc) return rc;
   c->stage = 3;
@@ -523,6 +591,45 @@ int higs_get_counts(higs_ctx* c, higs_counts* out) {
   return HIGS_OK;
 }
 
+namespace {
+// Segmented sort read-back: pairs as macro-tile << 32 | depth bits and ids,
+// rebuilt from the segment offsets (PAIRS: the filled composites, in segment
+// order; SORTED: the sorted ids with each id's depth bits).
+int seg_debug_pairs(higs_ctx* c, int which, const DeviceCounters& h, size_t np, char* dst,
+                    size_t bytes) {
+  std::vector<uint32_t> off((size_t)c->n_mt + 1);
+  if (hipMemcpy(off.data(), c->mt_off, off.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return HIGS_E_HIP;
+  uint32_t gbits = 0;
+  for (int64_t v = c->n > 1 ? c->n - 1 : 0; v; v >>= 1) ++gbits;
+  std::vector<uint64_t> keys(np);
+  std::vector<uint32_t> ids(np);
+  if (which == HIGS_DBG_PAIRS) {
+    if (!(c->debug_flags & HIGS_DEBUG_KEEP_PAIRS) || !c->dbg_keys) return HIGS_E_STATE;
+    std::vector<uint64_t> comp(np);
+    if (np && hipMemcpy(comp.data(), c->dbg_keys, np * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      return HIGS_E_HIP;
+    for (size_t q = 0; q < np; ++q) {
+      ids[q] = (uint32_t)(comp[q] & ((1ull << gbits) - 1ull));
+      keys[q] = (uint32_t)((comp[q] >> gbits) + h.key_min);
+    }
+  } else {
+    std::vector<uint32_t> fkey((size_t)c->n);
+    if (np && hipMemcpy(ids.data(), c->vals[0], np * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return HIGS_E_HIP;
+    if (c->n && hipMemcpy(fkey.data(), c->f_key, (size_t)c->n * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return HIGS_E_HIP;
+    for (size_t q = 0; q < np; ++q) keys[q] = ids[q] < (uint32_t)c->n ? fkey[ids[q]] : 0u;
+  }
+  for (int m = 0; m < c->n_mt; ++m)
+    for (uint32_t q = off[m]; q < off[m + 1] && q < np; ++q) keys[q] |= (uint64_t)m << 32;
+  const size_t kb = bytes < np * 8 ? bytes : np * 8;
+  memcpy(dst, keys.data(), kb);
+  if (bytes > np * 8) memcpy(dst + np * 8, ids.data(), bytes - np * 8);
+  return HIGS_OK;
+}
+}  // namespace
+
 int higs_debug_copy(higs_ctx* c, int which, void* host_dst, size_t bytes) {
   if (!c || !host_dst) return HIGS_E_INVALID;
   DeviceGuard g(c->device);
@@ -554,6 +661,7 @@ int higs_debug_copy(higs_ctx* c, int which, void* host_dst, size_t bytes) {
     case HIGS_DBG_PAIRS:
     case HIGS_DBG_SORTED: {
       if (c->stage < 2 || bytes > np * 12) return HIGS_E_INVALID;
+      if (c->segmented()) return seg_debug_pairs(c, which, h, np, dst, bytes);
       const uint64_t* k;
       const uint32_t* v;
       if (which == HIGS_DBG_PAIRS) {

@@ -28,6 +28,11 @@ constexpr int kSortItems = 16;                         // keys per thread
 constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys per tile
 constexpr int kMaxPasses = 8;
 
+// Segmented sort geometry.
+constexpr int kSegBatch = 8192;     // B_p, gaussians per partition batch (sec. 4.3)
+constexpr int kSegMaxLevels = 20;   // merge levels of the largest possible segment
+constexpr int kSegMaxMt = 20480;    // macro-tiles whose two LDS tables fit 160 KiB
+
 // Raster record written by the projection for every visible gaussian and
 // gathered by the rasteriser: 48 bytes, three 16-byte loads.
 struct alignas(16) RasterRecord {
@@ -58,7 +63,9 @@ struct DeviceCounters {
   uint32_t key_min;         // smallest / largest float32 depth bits of the
   uint32_t key_max;         //   frame's visible gaussians (key compression)
   uint32_t bwd_next;        // work counter of the persistent raster adjoint
-  uint32_t pad[9];
+  uint32_t seg_max;         // largest segment (segmented sort)
+  uint32_t seg_next[1 + 20];  // work counters: chunk sort, then one per merge level
+  uint32_t pad[8];
 };
 
 // Look-back status words (sort passes): 30-bit epoch,
@@ -93,7 +100,8 @@ struct ParamArgs {
 };
 
 // ---- host-side launchers (one translation unit each) ----------------------
-hipError_t launch_clear(DeviceCounters* dc, uint32_t* hist, int n_hist, hipStream_t s);
+hipError_t launch_clear(DeviceCounters* dc, uint32_t* hist, int n_hist, uint32_t* seg_count,
+                        int n_seg, hipStream_t s);
 
 hipError_t launch_project(int64_t n, const float* means, const float* scales, const float* quats,
                           const float* opac, const float* sh, CamArgs cam, ParamArgs prm,
@@ -146,6 +154,34 @@ hipError_t launch_backward(int64_t n, const float* means, const float* scales, c
                            const float* dT, float2* state, float* dgeo, float* dmeans,
                            float* dscales, float* dquats, float* dopac, float* dsh, int n_cus,
                            hipStream_t s);
+
+struct SegBuffers {
+  uint32_t* seg_count;  // [n_mt] pairs per macro-tile
+  uint32_t* cursor;     // [n_mt] fill cursors
+  uint32_t* mt_off;     // [n_mt + 1] segment offsets
+  uint32_t* chunk_off;  // [n_mt + 1] first sort chunk of each segment
+  uint32_t* blk_off;    // [n_mt + 1] first merge block of each multi-chunk segment
+  uint64_t* comp;       // [max_pairs] composites as filled, then a merge buffer
+  uint64_t* runs;       // [max_pairs] sorted runs / merge buffer
+  uint32_t* ids;        // [max_pairs] output: ids in (macro-tile, depth, id) order
+};
+// Binning into segments: per-macro-tile counts and their scan, then the fill
+// of composites; then the sort of every segment (chunk sort, merge levels).
+hipError_t launch_seg_count(int64_t n, CamArgs cam, const float* f_mx, const float* f_my,
+                            const float* f_a, const float* f_b, const float* f_c,
+                            const float* f_tau, const uint32_t* f_cnt, SegBuffers sb,
+                            uint32_t max_pairs, DeviceCounters* dc, hipStream_t s);
+hipError_t launch_seg_fill(int64_t n, CamArgs cam, const float* f_mx, const float* f_my,
+                           const float* f_a, const float* f_b, const float* f_c, const float* f_tau,
+                           const uint32_t* f_key, const uint32_t* f_cnt, SegBuffers sb,
+                           uint32_t max_pairs, DeviceCounters* dc, hipStream_t s);
+hipError_t launch_seg_sort(int64_t n, int n_mt, SegBuffers sb, uint32_t max_pairs,
+                           DeviceCounters* dc, int n_cus, hipStream_t s);
+
+// Batch table from segment offsets already computed (segmented sort).
+hipError_t launch_batch_from_offsets(int n_mt, uint32_t batch_cap, uint32_t max_batches,
+                                     DeviceCounters* dc, const uint32_t* mt_off,
+                                     uint32_t* batch_first, uint32_t* batch_tab, hipStream_t s);
 
 int raster_workers_per_cu();
 

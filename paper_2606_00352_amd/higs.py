@@ -19,6 +19,7 @@ OK, E_INVALID, E_NOMEM, E_CAPACITY, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -
 OVF_PAIRS, OVF_BATCHES = 1, 2
 DBG_PROJ, DBG_RECORDS, DBG_PAIRS, DBG_SORTED, DBG_MT_OFFSETS, DBG_BATCHES, DBG_ACTIVE, DBG_PARTIALS = range(1, 9)
 DEBUG_KEEP_PAIRS, DEBUG_COUNT_EVALS = 1, 2
+SORT_SEGMENTED, SORT_ONESWEEP = 0, 1
 TIMER_NAMES = ("project", "scan", "fill", "sort", "batch", "raster", "merge")
 
 # every symbol include/higs.h declares
@@ -41,7 +42,7 @@ class Params(ctypes.Structure):
                 ("mt_tiles_y", ctypes.c_int32), ("batch_cap", ctypes.c_int32),
                 ("sh_degree", ctypes.c_int32), ("alpha_max", ctypes.c_float),
                 ("t_eps", ctypes.c_float), ("near_z", ctypes.c_float),
-                ("dilation", ctypes.c_float)]
+                ("dilation", ctypes.c_float), ("sort_mode", ctypes.c_int32)]
 
 
 class CameraC(ctypes.Structure):

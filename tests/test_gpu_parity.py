@@ -15,9 +15,12 @@ from tests import gpu_common as gc
 pytestmark = pytest.mark.gpu
 
 
-def _full_check(orc, scene, cam, cap=1024, report=None, check_partials=True):
+SORT_MODES = pytest.mark.parametrize("sort_mode", [0, 1], ids=["segmented", "onesweep"])
+
+
+def _full_check(orc, scene, cam, cap=1024, report=None, check_partials=True, sort_mode=0):
     report = {} if report is None else report
-    ctx, img, T = gc.gpu_frame(scene, cam, batch_cap=cap)
+    ctx, img, T = gc.gpu_frame(scene, cam, batch_cap=cap, sort_mode=sort_mode)
     prm = gc.oracle_params(orc, batch_cap=cap)
     fr = orc.frame(scene, cam, prm)
     gc.check_projection(orc, ctx, fr, report)
@@ -48,34 +51,38 @@ def _full_check(orc, scene, cam, cap=1024, report=None, check_partials=True):
     return ctx, report
 
 
-def test_config0_all_stages(orc):
+@SORT_MODES
+def test_config0_all_stages(orc, sort_mode):
     sc, cams = scenes.config0()
-    ctx, rep = _full_check(orc, sc, cams[0])
+    ctx, rep = _full_check(orc, sc, cams[0], sort_mode=sort_mode)
     c = ctx.counts()
     assert c.n_pairs > 10_000 and c.n_batches > 30
     print("config0", rep)
 
 
 @pytest.mark.parametrize("cap", [4, 64, 333])
-def test_small_batch_caps(orc, cap):
+@SORT_MODES
+def test_small_batch_caps(orc, cap, sort_mode):
     sc, cams = scenes.config0()
-    _full_check(orc, sc, cams[0], cap=cap, check_partials=(cap != 4))
+    _full_check(orc, sc, cams[0], cap=cap, check_partials=(cap != 4), sort_mode=sort_mode)
 
 
 @pytest.mark.parametrize("W,H", [(200, 150), (130, 70), (250, 171)])
-def test_ragged_images(orc, W, H):
+@SORT_MODES
+def test_ragged_images(orc, sort_mode, W, H):
     """Widths/heights that are not multiples of the macro-tile (64x32) or of
     the render tile (8x8)."""
     sc = scenes.uniform_scene(6000, seed=W + H)
     cam = scenes.camera_at_origin(W, H, 0.9 * W, (0.2, 0.4, 0.1))
-    _full_check(orc, sc, cam)
+    _full_check(orc, sc, cam, sort_mode=sort_mode)
 
 
-def test_orbit_camera_clustered(orc):
+@SORT_MODES
+def test_orbit_camera_clustered(orc, sort_mode):
     """Rotated camera, clustered scene (config-1 generator at a small size)."""
     sc = scenes.clustered_scene(60_000, seed=5, n_clusters=20)
     cam = scenes.orbit_cameras(3, 7, 320, 180, 200.0)[1]
-    _full_check(orc, sc, cam)
+    _full_check(orc, sc, cam, sort_mode=sort_mode)
 
 
 def test_empty_and_single(orc):
@@ -133,7 +140,8 @@ def test_edge_straddling_and_huge_splat(orc):
     assert cnt[k] == ctx.n_mt
 
 
-def test_equal_depths_tie_break(orc):
+@SORT_MODES
+def test_equal_depths_tie_break(orc, sort_mode):
     """2,000 gaussians at one depth: ties resolved by gaussian id."""
     rng = np.random.default_rng(2)
     n = 2000
@@ -141,14 +149,15 @@ def test_equal_depths_tie_break(orc):
     sc.means[:, 2] = 3.0
     sc.means[:, :2] = rng.uniform(-0.5, 0.5, (n, 2))
     cam = scenes.camera_at_origin(160, 160, 160.0)
-    ctx, _ = _full_check(orc, sc, cam)
+    ctx, _ = _full_check(orc, sc, cam, sort_mode=sort_mode)
     keys, vals = ctx.sorted_pairs()
     mts = (keys >> np.uint64(32)).astype(np.int64)
     for m in np.unique(mts):
         assert np.all(np.diff(vals[mts == m].astype(np.int64)) > 0)
 
 
-def test_dense_macro_tile_many_batches(orc):
+@SORT_MODES
+def test_dense_macro_tile_many_batches(orc, sort_mode):
     """> 8,000 gaussians in one macro-tile (several 1,024-batches and several
     4,096-key sort tiles inside one segment)."""
     n = 9000
@@ -160,7 +169,7 @@ def test_dense_macro_tile_many_batches(orc):
     sc.means[:, 2] = z
     sc.scales[:] = 0.004
     cam = scenes.camera_at_origin(256, 128, 256.0)
-    ctx, _ = _full_check(orc, sc, cam)
+    ctx, _ = _full_check(orc, sc, cam, sort_mode=sort_mode)
     c = ctx.counts()
     assert c.n_batches >= 9
 
@@ -193,3 +202,35 @@ def test_untiled_definition_within_eps(orc):
     cmax = max(float(geo[valid == 1, orc.G_R:orc.G_BL + 1].max()), 0.1)
     d = np.abs(img - o_img)[amb == 0]
     assert d.max() <= 1e-4 * cmax + 2e-5
+
+
+@SORT_MODES
+def test_one_segment_of_forty_thousand(orc, sort_mode):
+    """40,000 gaussians in one 64x32 macro-tile: a segment of five 8,192-key
+    chunks, merged over three levels (an odd run at each) in the segmented
+    sort."""
+    n = 40_000
+    sc = scenes.uniform_scene(n, seed=21)
+    rng = np.random.default_rng(21)
+    z = rng.uniform(2, 6, n).astype(np.float32)
+    sc.means[:, 0] = rng.uniform(-30, 30, n) * z / 64.0
+    sc.means[:, 1] = rng.uniform(-14, 14, n) * z / 64.0
+    sc.means[:, 2] = z
+    sc.scales[:] = 0.003
+    cam = scenes.camera_at_origin(64, 32, 64.0)
+    ctx, _ = _full_check(orc, sc, cam, sort_mode=sort_mode, check_partials=False)
+    assert ctx.counts().n_pairs > 32768
+
+
+def test_sort_modes_give_identical_frames(orc):
+    """Both sort implementations: the same ids, batches and image, bit for bit."""
+    sc = scenes.clustered_scene(120_000, seed=17, n_clusters=12)
+    cam = scenes.orbit_cameras(4, 9, 400, 300, 300.0)[2]
+    out = []
+    for mode in (0, 1):
+        ctx, img, T = gc.gpu_frame(sc, cam, sort_mode=mode)
+        out.append((ctx.sorted_pairs(), ctx.batches(), img, T))
+    (k0, v0), b0, i0, t0 = out[0]
+    (k1, v1), b1, i1, t1 = out[1]
+    assert np.array_equal(k0, k1) and np.array_equal(v0, v1) and np.array_equal(b0, b1)
+    assert np.array_equal(i0, i1) and np.array_equal(t0, t1)
