@@ -58,7 +58,8 @@ MEASURED_TRAFFIC = {
              "bytes_per_launch": 1232807136},
 }
 KERNEL_SOURCES = {"project": ("project.hip", "predicate.h"), "fill": ("emit.hip", "predicate.h"),
-                  "sort": ("sort.hip",), "raster": ("raster.hip", "raster_common.h")}
+                  "sort": ("sort.hip",), "raster": ("raster.hip", "raster_common.h"),
+                  "seg_fill": ("segsort.hip", "predicate.h"), "seg_sort": ("segsort.hip",)}
 
 
 def kernel_source_sha(kernel):
@@ -68,6 +69,12 @@ def kernel_source_sha(kernel):
         with open(os.path.join(ROOT, "paper_2606_00352_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def traffic_key(stage, segmented):
+    """Counter entry of a stage: binning and sort run other kernels in
+    segmented mode."""
+    return "seg_" + stage if segmented and stage in ("fill", "sort") else stage
 
 
 def measured_traffic(kernel):
@@ -235,6 +242,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--sort", choices=("onesweep", "segmented"), default="onesweep",
+                    help="depth-ordering of the pairs: global radix sort or per-macro-tile segments")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the frame path is single-GPU; --gpus must be 1", file=sys.stderr)
@@ -260,8 +269,9 @@ def main():
 
     # size the context from a first frame of every view (grow on overflow)
     max_pairs = 3 * scene.n
+    sort_mode = higs.SORT_SEGMENTED if args.sort == "segmented" else higs.SORT_ONESWEEP
     while True:
-        ctx = higs.Context(scene.n, 1920, 1080, max_pairs=max_pairs)
+        ctx = higs.Context(scene.n, 1920, 1080, max_pairs=max_pairs, sort_mode=sort_mode)
         image = torch.empty((1080, 1920, 3), dtype=torch.float32, device="cuda:0")
         worst = 0
         ok = True
@@ -311,13 +321,18 @@ def main():
     mean = {k: float(np.mean(v)) for k, v in sizes.items()}
     n = scene.n
     rl = {}
+    seg = args.sort == "segmented"
     # fill: reads the pair count of every gaussian (4 B) and the six binning
-    # fields and depth key of every visible one (28 B); writes 12 B per pair
-    fill_bytes = 4 * n + 28 * mean["visible"] + 12 * mean["pairs"]
+    # fields and depth key of every visible one (28 B); writes a 12-B (key, id)
+    # pair, or in segmented mode one 8-B composite, per pair
+    fill_bytes = 4 * n + 28 * mean["visible"] + (8 if seg else 12) * mean["pairs"]
     rl["fill"] = ("hbm", fill_bytes / (timers["fill"] * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", fill_bytes)
     proj_bytes = PROJECT_B_PER_GAUSSIAN * n + PROJECT_B_PER_VISIBLE * mean["visible"]
     rl["project"] = ("hbm", proj_bytes / (timers["project"] * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", proj_bytes)
-    sort_bytes = mean["pairs"] * (8 + 24 * mean["passes"])
+    # onesweep: the digit histogram reads every key (8 B), each moving pass
+    # reads and writes key and id (24 B); segmented: every composite read once
+    # (8 B) and its id written once (4 B), the floor of any segment sort
+    sort_bytes = mean["pairs"] * (12 if seg else 8 + 24 * mean["passes"])
     rl["sort"] = ("hbm", sort_bytes / (timers["sort"] * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", sort_bytes)
     ops = mean["evals"] * RASTER_OPS_PER_EVAL
     rl["raster"] = ("alu", ops / (timers["raster"] * 1e-3) / 1e12, VALU_PEAK_TOPS, "Tops/s", ops)
@@ -339,17 +354,18 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "5.8M clustered gaussians (SH degree 3), 1920x1080, 60-view orbit, f=1100",
-                   "gaussians": n, "width": 1920, "height": 1080, "views": len(cams),
+                   "gaussians": n, "width": 1920, "height": 1080, "views": len(cams), "sort": args.sort,
                    "mean_visible": round(mean["visible"]), "mean_pairs": round(mean["pairs"]),
                    "mean_batches": round(mean["batches"]), "mean_sort_passes": mean["passes"],
                    "kernel_ms": {k: round(v, 4) for k, v in timers.items()},
                    "sort_pairs_per_s": round(mean["pairs"] / (timers["sort"] * 1e-3)),
                    "stage_roofline": {k: {"bound": b, "achieved": round(a, 2), "peak": round(p, 2),
                                           "unit": u, "frac": round(a / p, 4),
-                                          "traffic": measured_traffic(k)}
+                                          "traffic": measured_traffic(traffic_key(k, seg))}
                                       for k, (b, a, p, u, w) in rl.items()}},
         "roofline": {"kernel": dom, "bound": bound, "achieved": round(ach, 2), "peak": round(peak, 2),
-                     "unit": unit, "frac": round(ach / peak, 4), "traffic": measured_traffic(dom)},
+                     "unit": unit, "frac": round(ach / peak, 4),
+                     "traffic": measured_traffic(traffic_key(dom, seg))},
     }
     if not args.no_backward:
         log("backward leg")

@@ -145,10 +145,10 @@ __device__ __forceinline__ bool geometry(float3 mean, float3 scale, float4 quat,
 __device__ __forceinline__ float3 operator*(float s, float3 v) { return make_float3(s * v.x, s * v.y, s * v.z); }
 __device__ __forceinline__ float3 operator+(float3 a, float3 b) { return make_float3(a.x + b.x, a.y + b.y, a.z + b.z); }
 
-// View-dependent colour, float32: rgb = max(0, 0.5 + sum_k Y_k(d) sh_k).
-__device__ __forceinline__ float3 sh_colour(const float* __restrict__ sh, int degree, float x,
-                                            float y, float z) {
-  auto co = [&](int k) { return make_float3(sh[3 * k + 0], sh[3 * k + 1], sh[3 * k + 2]); };
+// View-dependent colour, float32: rgb = max(0, 0.5 + sum_k Y_k(d) sh_k);
+// co(k) gives coefficient k.
+template <class Co>
+__device__ __forceinline__ float3 sh_colour(Co&& co, int degree, float x, float y, float z) {
   float3 acc = kY00 * co(0);
   if (degree >= 1) {
     acc = acc + (-kY1 * y) * co(1) + (kY1 * z) * co(2) + (-kY1 * x) * co(3);
@@ -177,12 +177,22 @@ project_kernel(int64_t n, const float* __restrict__ means, const float* __restri
                float* __restrict__ f_b, float* __restrict__ f_c, float* __restrict__ f_tau,
                uint32_t* __restrict__ f_key, uint32_t* __restrict__ f_cnt,
                RasterRecord* __restrict__ rec, uint32_t* __restrict__ block_sums,
-               DeviceCounters* __restrict__ dc) {
+               DeviceCounters* __restrict__ dc, bool sh_vec4) {
   __shared__ uint32_t wave_min[kProjBlock / 64], wave_max[kProjBlock / 64];
   __shared__ uint32_t wave_sums[2][kProjBlock / 64];
   const int64_t i = (int64_t)blockIdx.x * kProjBlock + threadIdx.x;
   uint32_t cnt = 0;
   uint32_t kmin = 0xffffffffu, kmax = 0u;
+  // degree 3 with a 16-byte aligned sh array: the 48 coefficients (192
+  // bytes) are loaded before the geometry, so that the loads overlap its
+  // arithmetic
+  float4 shv[12];
+  const bool early = sh_vec4 && prm.sh_degree == 3 && i < n;
+  if (early) {
+    const float4* src = reinterpret_cast<const float4*>(sh + 48 * i);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) shv[k] = src[k];
+  }
   if (i < n) {
     const float3 mean = make_float3(means[3 * i + 0], means[3 * i + 1], means[3 * i + 2]);
     const float3 scale = make_float3(scales[3 * i + 0], scales[3 * i + 1], scales[3 * i + 2]);
@@ -219,7 +229,16 @@ project_kernel(int64_t n, const float* __restrict__ means, const float* __restri
           dy *= inv;
           dz *= inv;
         }
-        const float3 rgb = sh_colour(sh + (int64_t)ncoef * 3 * i, prm.sh_degree, dx, dy, dz);
+        float3 rgb;
+        if (early) {
+          const float* c = reinterpret_cast<const float*>(shv);
+          rgb = sh_colour([&](int k) { return make_float3(c[3 * k], c[3 * k + 1], c[3 * k + 2]); },
+                          3, dx, dy, dz);
+        } else {
+          const float* c = sh + (int64_t)ncoef * 3 * i;
+          rgb = sh_colour([&](int k) { return make_float3(c[3 * k], c[3 * k + 1], c[3 * k + 2]); },
+                          prm.sh_degree, dx, dy, dz);
+        }
         RasterRecord r;
         r.mx = f.mx;
         r.my = f.my;
@@ -301,7 +320,8 @@ hipError_t launch_project(int64_t n, const float* means, const float* scales, co
   const unsigned blocks = (unsigned)((n + kProjBlock - 1) / kProjBlock);
   hipLaunchKernelGGL(project_kernel, dim3(blocks), dim3(kProjBlock), 0, s, n, means, scales,
                      quats, opac, sh, cam, prm, campos, f_mx, f_my,
-                     f_a, f_b, f_c, f_tau, f_key, f_cnt, rec, block_sums, dc);
+                     f_a, f_b, f_c, f_tau, f_key, f_cnt, rec, block_sums, dc,
+                     (reinterpret_cast<uintptr_t>(sh) & 15u) == 0);
   return hipGetLastError();
 }
 

@@ -1,6 +1,6 @@
 """GPU parity at the benchmark's full sizes, in the benchmark's launch
-configuration (default context, batch cap 1,024, persistent kernels over all
-CUs): the 5.8M-gaussian 1080p frame and the 6M-gaussian 4K frame.
+configuration (batch cap 1,024, persistent kernels over all CUs), in both sort
+modes: the 5.8M-gaussian 1080p frame and the 6M-gaussian 4K frame.
 
 Every discrete output is compared in full (projection fields, the sorted pair
 list, macro-tile offsets, batch table: bit-exact); the image is compared on
@@ -26,35 +26,43 @@ def _sample_pixels(rng, fr, cam, k):
 
 
 def _full(orc, scene, cam, n_random, n_untiled):
+    """Both sort modes against one oracle frame."""
     import torch
     from paper_2606_00352_amd import higs
     gc.need_gpu()
-    ctx = higs.Context(scene.n, cam.width, cam.height, max_pairs=4 * scene.n)
     t = higs.scene_tensors(scene)
-    img, T = higs.render(ctx, t, cam)
-    torch.cuda.synchronize()
-    c = ctx.counts()
-    assert c.overflow == 0
-    img, T = img.cpu().numpy(), T.cpu().numpy()
     fr = orc.frame(scene, cam, render=False)
-    report = {}
-    gc.check_projection(orc, ctx, fr, report)
-    gc.check_pairs_sort_batches(orc, ctx, fr, 1024, check_emission=False)
     rng = np.random.default_rng(0)
     pix = _sample_pixels(rng, fr, cam, n_random)
     o_img, o_T, amb = orc.render_tiled(fr.geo, fr.sorted_gid, fr.mt_off, fr.batch_tab, cam, pixels=pix)
-    g_img = img[pix[:, 1], pix[:, 0]].astype(np.float64)
-    g_T = T[pix[:, 1], pix[:, 0]].astype(np.float64)
-    cmax = float(fr.geo[fr.valid == 1, orc.G_R:orc.G_BL + 1].max())
-    gc.check_image(g_img, g_T, o_img, o_T, amb, report, cmax)
-    # the plain definition (every gaussian, per pixel) on a few pixels
     sub = pix[rng.choice(pix.shape[0], n_untiled, replace=False)]
     u_img, u_T, u_amb = orc.render_untiled(fr.valid, fr.geo, cam, pixels=sub)
-    d = np.abs(img[sub[:, 1], sub[:, 0]] - u_img)[u_amb == 0]
-    assert d.max(initial=0.0) <= 1e-4 * max(cmax, 1.0) + 2e-5
-    assert np.all((T >= 0) & (T <= 1))
-    report.update(pairs=int(c.n_pairs), batches=int(c.n_batches), visible=int(c.n_visible))
-    print(report)
+    cmax = float(fr.geo[fr.valid == 1, orc.G_R:orc.G_BL + 1].max())
+    images = []
+    for mode in (higs.SORT_ONESWEEP, higs.SORT_SEGMENTED):
+        print(f"sort mode {mode}", flush=True)
+        ctx = higs.Context(scene.n, cam.width, cam.height, max_pairs=4 * scene.n, sort_mode=mode)
+        img, T = higs.render(ctx, t, cam)
+        torch.cuda.synchronize()
+        c = ctx.counts()
+        assert c.overflow == 0
+        img, T = img.cpu().numpy(), T.cpu().numpy()
+        report = {}
+        gc.check_projection(orc, ctx, fr, report)
+        gc.check_pairs_sort_batches(orc, ctx, fr, 1024, check_emission=False)
+        g_img = img[pix[:, 1], pix[:, 0]].astype(np.float64)
+        g_T = T[pix[:, 1], pix[:, 0]].astype(np.float64)
+        gc.check_image(g_img, g_T, o_img, o_T, amb, report, cmax)
+        # the plain definition (every gaussian, per pixel) on a few pixels
+        d = np.abs(img[sub[:, 1], sub[:, 0]] - u_img)[u_amb == 0]
+        assert d.max(initial=0.0) <= 1e-4 * max(cmax, 1.0) + 2e-5
+        assert np.all((T >= 0) & (T <= 1))
+        report.update(mode=mode, pairs=int(c.n_pairs), batches=int(c.n_batches), visible=int(c.n_visible))
+        print(report, flush=True)
+        images.append((img, T))
+        ctx.close()
+    # the two orders are the same order: identical frames
+    assert np.array_equal(images[0][0], images[1][0]) and np.array_equal(images[0][1], images[1][1])
     return c
 
 
