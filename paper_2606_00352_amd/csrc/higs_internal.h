@@ -24,8 +24,8 @@ constexpr int kProjBlock = 256;  // gaussians per projection / emission block
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;                         // keys per thread
-constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys per tile
+constexpr int kSortItems = 24;                         // keys per thread
+constexpr int kSortTile = kSortThreads * kSortItems;  // 6144 keys per tile
 constexpr int kMaxPasses = 8;
 
 // Segmented sort geometry.

@@ -2,13 +2,14 @@
 // macro-tile's list ordered by depth; ties by gaussian id).
 //
 // A stable least-significant-digit radix sort over the composite 64-bit key
-// (macro-tile << 32 | float32 depth bits) with the gaussian id as value.
-// Pairs arrive in gaussian-id order and every pass is stable, so the result
-// is ordered by (macro-tile, depth, id).  One pass per 8-bit digit of the
-// 32 + ceil(log2 n_mt) significant key bits, each a single "onesweep" kernel:
-//   - a persistent grid claims 4096-key tiles from a device counter, so tile
+// (macro-tile << d | depth bits - min, d the bits of the frame's depth range)
+// with the gaussian id as value.  Pairs arrive in gaussian-id order and every
+// pass is stable, so the result is ordered by (macro-tile, depth, id).  One
+// pass per 8-bit digit of the d + ceil(log2 n_mt) significant key bits, each a
+// single "onesweep" kernel:
+//   - a persistent grid claims 6144-key tiles from a device counter, so tile
 //     t's predecessors are always resident (forward progress of the look-back);
-//   - each wave ranks its 1024 keys stably with 8 ballots per key (wave-level
+//   - each wave ranks its 1536 keys stably with 8 ballots per key (wave-level
 //     multisplit) against a wave-private digit histogram in LDS;
 //   - per digit, the tile publishes its count and looks back over the
 //     preceding tiles' published counts/prefixes (decoupled look-back, one
@@ -99,7 +100,7 @@ sort_plan_kernel(const uint32_t* __restrict__ hist, DeviceCounters* __restrict__
 }
 
 constexpr int kWaves = kSortThreads / 64;
-constexpr int kWaveItems = 64 * kSortItems;  // 1024 keys per wave
+constexpr int kWaveItems = 64 * kSortItems;  // 1536 keys per wave
 
 struct SortLds {
   // the tile regrouped by digit: keys first, then (reusing the space) values

@@ -158,8 +158,8 @@ def test_equal_depths_tie_break(orc, sort_mode):
 
 @SORT_MODES
 def test_dense_macro_tile_many_batches(orc, sort_mode):
-    """> 8,000 gaussians in one macro-tile (several 1,024-batches and several
-    4,096-key sort tiles inside one segment)."""
+    """> 8,000 gaussians in one macro-tile (several 1,024-batches and more than
+    one sort tile inside one segment)."""
     n = 9000
     sc = scenes.uniform_scene(n, seed=21)
     rng = np.random.default_rng(21)
