@@ -50,44 +50,87 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 }
 
 // One workgroup of 1024 threads: exclusive scan of the per-block (pairs,
-// visible) sums in place; writes the frame totals.
+// visible) sums in place; writes the frame totals.  The sums are read in
+// chunks of 1024 x 16 blocks, each thread taking 16 consecutive blocks with
+// eight 16-byte loads (coalesced across the wave, all in flight at once); a
+// block-wide scan of the thread totals plus the carry of the earlier chunks
+// gives each thread its start.
 constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 16;  // blocks per thread per chunk
 __global__ void __launch_bounds__(kScanThreads)
 scan_kernel(uint32_t n_blocks, uint32_t* __restrict__ sums, uint32_t max_pairs,
             DeviceCounters* __restrict__ dc) {
   __shared__ uint32_t wave_tot[2][kScanThreads / 64];
-  const uint32_t per = (n_blocks + kScanThreads - 1) / kScanThreads;
-  const uint32_t b0 = threadIdx.x * per;
-  const uint32_t b1 = min(b0 + per, n_blocks);
-  uint32_t s_pairs = 0, s_vis = 0;
-  for (uint32_t b = b0; b < b1; ++b) {
-    s_pairs += sums[2 * b];
-    s_vis += sums[2 * b + 1];
-  }
-  const uint32_t ip = wave_incl_scan(s_pairs);
-  const uint32_t iv = wave_incl_scan(s_vis);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 63) {
-    wave_tot[0][wave] = ip;
-    wave_tot[1][wave] = iv;
+  uint32_t carry_p = 0, carry_v = 0;  // same in every thread
+  for (uint32_t c0 = 0; c0 < n_blocks; c0 += kScanThreads * kScanPer) {
+    const uint32_t b0 = c0 + threadIdx.x * kScanPer;
+    const bool full = b0 + kScanPer <= n_blocks;
+    uint32_t p[kScanPer], v[kScanPer];
+    if (full) {
+      const uint4* src = reinterpret_cast<const uint4*>(sums + 2 * (size_t)b0);
+#pragma unroll
+      for (int q = 0; q < kScanPer / 2; ++q) {
+        const uint4 x = src[q];
+        p[2 * q] = x.x;
+        v[2 * q] = x.y;
+        p[2 * q + 1] = x.z;
+        v[2 * q + 1] = x.w;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kScanPer; ++k) {
+        const uint32_t b = b0 + k;
+        p[k] = b < n_blocks ? sums[2 * (size_t)b] : 0u;
+        v[k] = b < n_blocks ? sums[2 * (size_t)b + 1] : 0u;
+      }
+    }
+    uint32_t sp = 0, sv = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      sp += p[k];
+      sv += v[k];
+    }
+    const uint32_t ip = wave_incl_scan(sp);
+    const uint32_t iv = wave_incl_scan(sv);
+    if (lane == 63) {
+      wave_tot[0][wave] = ip;
+      wave_tot[1][wave] = iv;
+    }
+    __syncthreads();
+    uint32_t base_p = carry_p, tot_p = 0, tot_v = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+      base_p += w < wave ? wave_tot[0][w] : 0u;
+      tot_p += wave_tot[0][w];
+      tot_v += wave_tot[1][w];
+    }
+    uint32_t run = base_p + ip - sp;
+    if (full) {
+      uint4* dst = reinterpret_cast<uint4*>(sums + 2 * (size_t)b0);
+#pragma unroll
+      for (int q = 0; q < kScanPer / 2; ++q) {
+        const uint32_t o0 = run;
+        const uint32_t o1 = run + p[2 * q];
+        run = o1 + p[2 * q + 1];
+        dst[q] = make_uint4(o0, v[2 * q], o1, v[2 * q + 1]);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kScanPer; ++k) {
+        if (b0 + k < n_blocks) sums[2 * (size_t)(b0 + k)] = run;
+        run += p[k];
+      }
+    }
+    carry_p += tot_p;
+    carry_v += tot_v;
+    __syncthreads();  // wave_tot is rewritten by the next chunk
   }
-  __syncthreads();
-  uint32_t base_p = 0, base_v = 0;
-  for (int w = 0; w < wave; ++w) {
-    base_p += wave_tot[0][w];
-    base_v += wave_tot[1][w];
-  }
-  uint32_t run = base_p + ip - s_pairs;
-  for (uint32_t b = b0; b < b1; ++b) {
-    const uint32_t v = sums[2 * b];
-    sums[2 * b] = run;
-    run += v;
-  }
-  if (threadIdx.x == kScanThreads - 1) {
-    const uint32_t total = base_p + ip;
+  if (threadIdx.x == 0) {
+    const uint32_t total = carry_p;
     dc->n_pairs_total = total;
     dc->n_pairs = total < max_pairs ? total : max_pairs;
-    dc->n_visible = base_v + iv;
+    dc->n_visible = carry_v;
     if (total > max_pairs) dc->overflow |= HIGS_OVF_PAIRS;
   }
 }
