@@ -172,7 +172,7 @@ raster_backward_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ 
           const int gi = k * 64 + j;
           const float al = eval_alpha(L.ga[gi], L.gb[gi], pxr, pyr, amax).al;
           if (T >= eps && al >= kAlphaMin) {
-            T = T * (1.0f - al);
+            T = fmaf(-al, T, T);  // the forward's update, bit for bit
             last = gi;
           }
         }
@@ -194,7 +194,7 @@ raster_backward_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ 
           const int gi = k * 64 + j;
           const float4 A = L.ga[gi];
           const float4 B = L.gb[gi];
-          const float bb = L.gc[gi];
+          const float bb = L.gc[gi].x;
           const PixelEval ev = eval_alpha(A, B, pxr, pyr, amax);
           const bool take = gi <= last && ev.al >= kAlphaMin;
           if (__ballot(take) == 0) continue;

@@ -16,7 +16,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 struct RasterLds {
   float4 ga[kMaxBatch];  // mx, my (macro-tile relative), l0', l1'
   float4 gb[kMaxBatch];  // l2', o, r, g
-  float gc[kMaxBatch];   // b
+  float4 gc[kMaxBatch];  // b, -, -, - (the stride of ga and gb: one address for all three reads)
   uint64_t masks[kMiniBatches][kTilesPerMt];
   uint32_t queue[kTilesPerMt];
   uint32_t qcount;
@@ -124,7 +124,7 @@ __device__ __forceinline__ uint32_t stage_unit(RasterLds& L, const UnitInfo& I,
       const float mxr = A.x - (float)I.x0, myr = A.y - (float)I.y0;
       L.ga[j] = make_float4(mxr, myr, A.z * kSqrtHalfLog2e, A.w * kSqrtHalfLog2e);
       L.gb[j] = make_float4(B.x * kSqrtHalfLog2e, B.y, B.z, B.w);
-      L.gc[j] = C.x;
+      L.gc[j].x = C.x;
       tmask = tile_overlap(mxr, myr, A.z, A.w, B.x, C.y, I.tiles_x, I.tiles_y);
     }
     uint64_t mine = 0;
