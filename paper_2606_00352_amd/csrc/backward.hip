@@ -170,7 +170,7 @@ raster_backward_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ 
           const int j = __ffsll((unsigned long long)m) - 1;
           m &= m - 1ull;
           const int gi = k * 64 + j;
-          const float al = eval_alpha(L.ga[gi], L.gb[gi], pxr, pyr, amax).al;
+          const float al = eval_alpha(L.ga[gi], L.gb[gi], L.gc[gi].y, pxr, pyr, amax).al;
           if (T >= eps && al >= kAlphaMin) {
             T = fmaf(-al, T, T);  // the forward's update, bit for bit
             last = gi;
@@ -194,8 +194,9 @@ raster_backward_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ 
           const int gi = k * 64 + j;
           const float4 A = L.ga[gi];
           const float4 B = L.gb[gi];
-          const float bb = L.gc[gi].x;
-          const PixelEval ev = eval_alpha(A, B, pxr, pyr, amax);
+          const float4 C = L.gc[gi];
+          const float bb = C.x;
+          const PixelEval ev = eval_alpha(A, B, C.y, pxr, pyr, amax);
           const bool take = gi <= last && ev.al >= kAlphaMin;
           if (__ballot(take) == 0) continue;
           float d0 = 0.0f, d1 = 0.0f, d2 = 0.0f, d3 = 0.0f, d4 = 0.0f, d5 = 0.0f, d6 = 0.0f,
@@ -212,8 +213,8 @@ raster_backward_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ 
             d6 = w * g0;
             d7 = w * g1;
             d8 = w * g2;
-            if (B.y * ev.e < amax) {  // alpha not clamped
-              d5 = dal * ev.e;
+            if (ev.e < amax) {  // alpha not clamped
+              d5 = dal * (ev.e / B.y);  // d alpha / d o = exp(-q/2); o > 0 for a listed gaussian
               const float dq = -dal * ev.al * kLn2f;  // dL/dq'
               const float du = 2.0f * ev.u * dq, dv = 2.0f * ev.v * dq;
               d2 = du * ev.dx;

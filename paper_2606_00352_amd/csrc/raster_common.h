@@ -16,7 +16,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 struct RasterLds {
   float4 ga[kMaxBatch];  // mx, my (macro-tile relative), l0', l1'
   float4 gb[kMaxBatch];  // l2', o, r, g
-  float4 gc[kMaxBatch];  // b, -, -, - (the stride of ga and gb: one address for all three reads)
+  float4 gc[kMaxBatch];  // b, log2 o, -, - (the stride of ga and gb: one address for all three reads)
   uint64_t masks[kMiniBatches][kTilesPerMt];
   uint32_t queue[kTilesPerMt];
   uint32_t qcount;
@@ -65,20 +65,21 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
 
 // alpha = min(alpha_max, o exp(-q/2)) at the pixel centre (pxr, pyr)
 // relative to the macro-tile, from the prescaled factors in LDS:
-// q' = (l0' dx + l1' dy)^2 + (l2' dy)^2 = q log2(e)/2, exp(-q/2) = exp2(-q').
+// q' = (l0' dx + l1' dy)^2 + (l2' dy)^2 = q log2(e)/2, and with the stored
+// lo = log2(o), o exp(-q/2) = exp2(lo - q') (the opacity rides in the
+// exponent: no multiply).  e is that unclamped alpha.
 struct PixelEval {
   float dx, dy, u, v, e, al;
 };
-__device__ __forceinline__ PixelEval eval_alpha(const float4& A, const float4& B, float pxr,
-                                                float pyr, float amax) {
+__device__ __forceinline__ PixelEval eval_alpha(const float4& A, const float4& B, float lo,
+                                                float pxr, float pyr, float amax) {
   PixelEval r;
   r.dx = pxr - A.x;
   r.dy = pyr - A.y;
   r.u = A.z * r.dx + A.w * r.dy;
   r.v = B.x * r.dy;
-  const float q = r.u * r.u + r.v * r.v;
-  r.e = __builtin_amdgcn_exp2f(-q);
-  r.al = fminf(amax, B.y * r.e);
+  r.e = __builtin_amdgcn_exp2f(fmaf(-r.u, r.u, fmaf(-r.v, r.v, lo)));
+  r.al = fminf(amax, r.e);
   return r;
 }
 
@@ -124,7 +125,7 @@ __device__ __forceinline__ uint32_t stage_unit(RasterLds& L, const UnitInfo& I,
       const float mxr = A.x - (float)I.x0, myr = A.y - (float)I.y0;
       L.ga[j] = make_float4(mxr, myr, A.z * kSqrtHalfLog2e, A.w * kSqrtHalfLog2e);
       L.gb[j] = make_float4(B.x * kSqrtHalfLog2e, B.y, B.z, B.w);
-      L.gc[j].x = C.x;
+      L.gc[j] = make_float4(C.x, __builtin_amdgcn_logf(B.y), 0.0f, 0.0f);  // b, log2 o
       tmask = tile_overlap(mxr, myr, A.z, A.w, B.x, C.y, I.tiles_x, I.tiles_y);
     }
     uint64_t mine = 0;
