@@ -5,9 +5,10 @@
 // that macro-tile with a 64-ary search (each step probes 64 evenly spaced
 // keys and keeps the bracket where the predicate flips), so a 10^7-pair list
 // takes four dependent loads per macro-tile.
-// `batch_table_kernel` (one workgroup): batches per macro-tile, their
-// exclusive scan (first batch of every macro-tile) and the (macro-tile,
-// start, length) rows in (macro-tile, batch) order.
+// `batch_table_kernel` (one workgroup): batches per macro-tile and their
+// exclusive scan (first batch of every macro-tile); `batch_rows_kernel` (a
+// wave per macro-tile) writes the (macro-tile, start, length) rows in
+// (macro-tile, batch) order.
 #include "higs_internal.h"
 
 namespace higs {
@@ -65,19 +66,8 @@ batch_table_kernel(int n_mt, uint32_t cap, uint32_t max_batches, const uint32_t*
   uint32_t run = v - mine;
   for (int w = 0; w < wave; ++w) run += wave_tot[w];
   for (int m = m0; m < m1; ++m) {
-    const uint32_t off = mt_off[m];
-    const uint32_t len = mt_off[m + 1] - off;
-    const uint32_t nb = (len + cap - 1) / cap;
     batch_first[m] = run;
-    for (uint32_t b = 0; b < nb; ++b) {
-      const uint32_t idx = run + b;
-      if (idx < max_batches) {
-        tab[3 * idx + 0] = (uint32_t)m;
-        tab[3 * idx + 1] = off + b * cap;
-        tab[3 * idx + 2] = min(cap, len - b * cap);
-      }
-    }
-    run += nb;
+    run += (mt_off[m + 1] - mt_off[m] + cap - 1) / cap;
   }
   if (threadIdx.x == kBtThreads - 1) {
     batch_first[n_mt] = run;
@@ -87,6 +77,41 @@ batch_table_kernel(int n_mt, uint32_t cap, uint32_t max_batches, const uint32_t*
   }
 }
 
+// The (macro-tile, start, length) rows: one wave per macro-tile, a lane per
+// batch.
+__global__ void __launch_bounds__(kOffThreads)
+batch_rows_kernel(int n_mt, uint32_t cap, uint32_t max_batches,
+                  const uint32_t* __restrict__ mt_off, const uint32_t* __restrict__ batch_first,
+                  uint32_t* __restrict__ tab) {
+  const int m = blockIdx.x * (kOffThreads / 64) + (threadIdx.x >> 6);
+  if (m >= n_mt) return;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t off = mt_off[m];
+  const uint32_t len = mt_off[m + 1] - off;
+  const uint32_t nb = (len + cap - 1) / cap;
+  const uint32_t first = batch_first[m];
+  for (uint32_t b = lane; b < nb; b += 64) {
+    const uint32_t idx = first + b;
+    if (idx < max_batches) {
+      tab[3 * idx + 0] = (uint32_t)m;
+      tab[3 * idx + 1] = off + b * cap;
+      tab[3 * idx + 2] = min(cap, len - b * cap);
+    }
+  }
+}
+
+// batch_first by one workgroup, then the rows by a wave per macro-tile
+static void launch_table(int n_mt, uint32_t batch_cap, uint32_t max_batches, DeviceCounters* dc,
+                         const uint32_t* mt_off, uint32_t* batch_first, uint32_t* batch_tab,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(batch_table_kernel, dim3(1), dim3(kBtThreads), 0, s, n_mt, batch_cap,
+                     max_batches, mt_off, dc, batch_first, batch_tab);
+  const int row_blocks = (n_mt + (kOffThreads / 64) - 1) / (kOffThreads / 64);
+  if (row_blocks > 0)
+    hipLaunchKernelGGL(batch_rows_kernel, dim3(row_blocks), dim3(kOffThreads), 0, s, n_mt,
+                       batch_cap, max_batches, mt_off, batch_first, batch_tab);
+}
+
 hipError_t launch_batch(int n_mt, uint32_t batch_cap, uint32_t max_batches, const uint64_t* const* keys2,
                         DeviceCounters* dc, uint32_t* mt_off, uint32_t* batch_first,
                         uint32_t* batch_tab, hipStream_t s) {
@@ -94,16 +119,14 @@ hipError_t launch_batch(int n_mt, uint32_t batch_cap, uint32_t max_batches, cons
   const int blocks = (waves + (kOffThreads / 64) - 1) / (kOffThreads / 64);
   hipLaunchKernelGGL(mt_offsets_kernel, dim3(blocks), dim3(kOffThreads), 0, s, n_mt, keys2[0],
                      keys2[1], dc, mt_off);
-  hipLaunchKernelGGL(batch_table_kernel, dim3(1), dim3(kBtThreads), 0, s, n_mt, batch_cap,
-                     max_batches, mt_off, dc, batch_first, batch_tab);
+  launch_table(n_mt, batch_cap, max_batches, dc, mt_off, batch_first, batch_tab, s);
   return hipGetLastError();
 }
 
 hipError_t launch_batch_from_offsets(int n_mt, uint32_t batch_cap, uint32_t max_batches,
                                      DeviceCounters* dc, const uint32_t* mt_off,
                                      uint32_t* batch_first, uint32_t* batch_tab, hipStream_t s) {
-  hipLaunchKernelGGL(batch_table_kernel, dim3(1), dim3(kBtThreads), 0, s, n_mt, batch_cap,
-                     max_batches, mt_off, dc, batch_first, batch_tab);
+  launch_table(n_mt, batch_cap, max_batches, dc, mt_off, batch_first, batch_tab, s);
   return hipGetLastError();
 }
 

@@ -113,17 +113,41 @@ merge_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ batch_firs
   const uint32_t b0 = min(batch_first[mt], nb), b1 = min(batch_first[mt + 1], nb);
   const float eps = prm.t_eps;
   float cr = 0.0f, cg = 0.0f, cb = 0.0f, T = 1.0f;
-  for (uint32_t b = b0; b < b1; ++b) {
-    if (!((active[b] >> t) & 1u)) continue;
-    const v4f p = __builtin_nontemporal_load(
+  auto load = [&](uint32_t b) {
+    return __builtin_nontemporal_load(
         reinterpret_cast<const v4f*>(partials + (((size_t)b * kTilesPerMt + t) * 64 + lane)));
-    if (T >= eps) {
-      cr += T * p.x;
-      cg += T * p.y;
-      cb += T * p.z;
-      T = T * p.w;
+  };
+  // the tile's active batches, 64 at a time (one activity word per lane);
+  // the next active partial is loaded before the current one is folded in
+  bool stop = false;
+  for (uint32_t c0 = b0; c0 < b1 && !stop; c0 += 64) {
+    const uint32_t bi = c0 + (uint32_t)lane;
+    uint64_t m = __ballot(bi < b1 && ((active[bi] >> t) & 1u));
+    if (!m) continue;
+    uint32_t b = c0 + (uint32_t)(__ffsll((unsigned long long)m) - 1);
+    m &= m - 1ull;
+    v4f p = load(b);
+    for (;;) {
+      const bool more = m != 0ull;
+      v4f pn = p;
+      if (more) {
+        b = c0 + (uint32_t)(__ffsll((unsigned long long)m) - 1);
+        m &= m - 1ull;
+        pn = load(b);
+      }
+      if (T >= eps) {
+        cr += T * p.x;
+        cg += T * p.y;
+        cb += T * p.z;
+        T = T * p.w;
+      }
+      if (__ballot(T >= eps) == 0) {
+        stop = true;
+        break;
+      }
+      if (!more) break;
+      p = pn;
     }
-    if (__ballot(T >= eps) == 0) break;
   }
   const int x = tx * kTile + (lane & 7), y = ty * kTile + (lane >> 3);
   if (x < cam.width && y < cam.height) {

@@ -37,6 +37,7 @@ __device__ __forceinline__ uint64_t status_word(uint32_t epoch, uint32_t flag, u
 
 constexpr int kHistThreads = 256;
 constexpr int kHistCopies = 8;  // LDS copies: lanes l and l+8k share one, 8-way at worst
+constexpr int kHistBatch = 8;   // keys loaded together per thread
 __global__ void __launch_bounds__(kHistThreads)
 sort_hist_kernel(const uint64_t* __restrict__ keys, const DeviceCounters* __restrict__ dc,
                  int n_passes, uint32_t* __restrict__ hist) {
@@ -48,10 +49,21 @@ sort_hist_kernel(const uint64_t* __restrict__ keys, const DeviceCounters* __rest
   __syncthreads();
   const uint32_t n = dc->n_pairs;
   uint32_t* mine = h[threadIdx.x & (kHistCopies - 1)];
-  for (uint32_t i = blockIdx.x * kHistThreads + threadIdx.x; i < n; i += gridDim.x * kHistThreads) {
-    const uint64_t key = keys[i];
-    for (int p = 0; p < n_passes; ++p)
-      atomicAdd(&mine[p * kRadix + (uint32_t)((key >> (kRadixBits * p)) & (kRadix - 1))], 1u);
+  // kHistBatch independent loads in flight per thread, then their counts
+  const uint32_t stride = gridDim.x * kHistThreads;
+  for (uint32_t i0 = blockIdx.x * kHistThreads + threadIdx.x; i0 < n; i0 += kHistBatch * stride) {
+    uint64_t key[kHistBatch];
+#pragma unroll
+    for (int b = 0; b < kHistBatch; ++b) {
+      const uint32_t i = i0 + (uint32_t)b * stride;
+      key[b] = i < n ? keys[i] : 0ull;
+    }
+#pragma unroll
+    for (int b = 0; b < kHistBatch; ++b) {
+      if (i0 + (uint32_t)b * stride >= n) break;
+      for (int p = 0; p < n_passes; ++p)
+        atomicAdd(&mine[p * kRadix + (uint32_t)((key[b] >> (kRadixBits * p)) & (kRadix - 1))], 1u);
+    }
   }
   __syncthreads();
   for (int k = threadIdx.x; k < n_passes * kRadix; k += kHistThreads) {
