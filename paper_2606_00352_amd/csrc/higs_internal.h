@@ -23,8 +23,8 @@ constexpr int kProjBlock = 256;  // gaussians per projection / emission block
 // Radix sort geometry.
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
-constexpr int kSortThreads = 256;
-constexpr int kSortItems = 24;                         // keys per thread
+constexpr int kSortThreads = 512;
+constexpr int kSortItems = 12;                         // keys per thread
 constexpr int kSortTile = kSortThreads * kSortItems;  // 6144 keys per tile
 constexpr int kMaxPasses = 8;
 

@@ -9,7 +9,7 @@
 // single "onesweep" kernel:
 //   - a persistent grid claims 6144-key tiles from a device counter, so tile
 //     t's predecessors are always resident (forward progress of the look-back);
-//   - each wave ranks its 1536 keys stably with 8 ballots per key (wave-level
+//   - each wave ranks its 768 keys stably with 8 ballots per key (wave-level
 //     multisplit) against a wave-private digit histogram in LDS;
 //   - per digit, the tile publishes its count and looks back over the
 //     preceding tiles' published counts/prefixes (decoupled look-back, one
@@ -112,7 +112,8 @@ sort_plan_kernel(const uint32_t* __restrict__ hist, DeviceCounters* __restrict__
 }
 
 constexpr int kWaves = kSortThreads / 64;
-constexpr int kWaveItems = 64 * kSortItems;  // 1536 keys per wave
+static_assert(kSortThreads >= kRadix && kSortThreads % 64 == 0, "one thread per digit, whole waves");
+constexpr int kWaveItems = 64 * kSortItems;  // 768 keys per wave
 
 struct SortLds {
   // the tile regrouped by digit: keys first, then (reusing the space) values
@@ -127,7 +128,9 @@ struct SortLds {
   uint32_t tile;
 };
 
-__global__ void __launch_bounds__(kSortThreads)
+// four waves per SIMD (two workgroups per CU): the register budget is held to
+// 128, which measured faster than more keys per thread at lower occupancy
+__global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)))
 onesweep_kernel(int pass, uint32_t epoch, uint64_t* __restrict__ k0, uint32_t* __restrict__ v0,
                 uint64_t* __restrict__ k1, uint32_t* __restrict__ v1,
                 const uint32_t* __restrict__ plan, const uint32_t* __restrict__ base,
@@ -186,10 +189,11 @@ onesweep_kernel(int pass, uint32_t epoch, uint64_t* __restrict__ k0, uint32_t* _
     }
     __syncthreads();
 
-    // per digit: wave prefixes, tile count, publish, look back
-    {
-      const int d = tid;  // kSortThreads == kRadix
-      uint32_t tot = 0;
+    // per digit (threads 0..255, whole waves): wave prefixes, tile count,
+    // publish, look back
+    const int d = tid;
+    uint32_t v = 0, tot = 0, prefix = 0;
+    if (tid < kRadix) {
 #pragma unroll
       for (int w = 0; w < kWaves; ++w) {
         const uint32_t c = L.whist[w][d];
@@ -200,14 +204,13 @@ onesweep_kernel(int pass, uint32_t epoch, uint64_t* __restrict__ k0, uint32_t* _
       if (tile == 0) st_status(st, status_word(epoch, kFlagPrefix, tot));
       else st_status(st, status_word(epoch, kFlagAggregate, tot));
       // exclusive scan of the tile's digit counts -> LDS slots
-      uint32_t v = tot;
+      v = tot;
 #pragma unroll
       for (int off = 1; off < 64; off <<= 1) {
         const uint32_t o = __shfl_up(v, off, 64);
         if (lane >= off) v += o;
       }
       if (lane == 63) L.wave_tot[wave] = v;
-      uint32_t prefix = 0;
       if (tile > 0) {
         int64_t t = (int64_t)tile - 1;
         uint32_t spins = 0;
@@ -227,7 +230,9 @@ onesweep_kernel(int pass, uint32_t epoch, uint64_t* __restrict__ k0, uint32_t* _
         }
         st_status(st, status_word(epoch, kFlagPrefix, prefix + tot));
       }
-      __syncthreads();
+    }
+    __syncthreads();
+    if (tid < kRadix) {
       uint32_t ls = v - tot;
       for (int w = 0; w < wave; ++w) ls += L.wave_tot[w];
       L.local_start[d] = ls;
