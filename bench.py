@@ -42,24 +42,28 @@ COPY_CALIBRATION_BYTES = 1 << 30
 # HBM traffic per launch of the dominant kernel, from two `rocprofv3 --pmc`
 # runs of this script (FETCH_SIZE, then WRITE_SIZE; mean over the timed frames,
 # scaled by the same counters' reading for the calibration copy).  Keyed by the
-# SHA-256 of the kernel's source file at the time the counters were taken: if
-# the source differs, the figure no longer describes the kernel and is
+# SHA-256 of the kernel's source files at the time the counters were taken: if
+# the sources differ, the figure no longer describes the kernel and is
 # reported as null.
 MEASURED_TRAFFIC = {
     # profiles/frame_1080p_5p8m_hbm_traffic.md (sort: histogram + plan + every
     # onesweep dispatch of a frame)
-    "raster": {"src_sha256": "6b4cefc39c36eefeab63a8777b0b4b6d6685ad5e175c8331064551d7265da7cb",
-               "bytes_per_launch": 1514105296},
-    "project": {"src_sha256": "955e069c36980c85778133b8d10294be94c4776d6b03d9a92ebd8efd3f90dcf4",
-                "bytes_per_launch": 1825441097},
-    "fill": {"src_sha256": "609e8597d94764ce66659993a8b308d9a6673c2051060c74109ad27851925f2e",
-             "bytes_per_launch": 284277598},
-    "sort": {"src_sha256": "afcf793b04b47a4e06b4cd00fe913615a7262a828752a740094afbbefcd25b59",
-             "bytes_per_launch": 1232807136},
+    "raster": {"src_sha256": "dda52f6a55eb7dd9a762be6ac3d9644973bd49dbd7cebb3be110740510d885b5",
+              "bytes_per_launch": 1513916906},
+    "project": {"src_sha256": "38cfb7009ccec5dcb9e24eb670cdaee7fd376ebebe7a5eb9afe8437934083c69",
+               "bytes_per_launch": 1830514020},
+    "fill": {"src_sha256": "5492682a75452826d7e5db1868ff98257f2bc0d942d59a1e2cde127048d94106",
+            "bytes_per_launch": 284277185},
+    "sort": {"src_sha256": "fccd3bfba2e534f9e8426384a2e7e5aa50a3123382e3740895468ae2fe3fb5a7",
+            "bytes_per_launch": 1175243839},
 }
-KERNEL_SOURCES = {"project": ("project.hip", "predicate.h"), "fill": ("emit.hip", "predicate.h"),
-                  "sort": ("sort.hip",), "raster": ("raster.hip", "raster_common.h"),
-                  "seg_fill": ("segsort.hip", "predicate.h"), "seg_sort": ("segsort.hip",)}
+# the sources each figure depends on (the shared header holds the kernels' shapes)
+KERNEL_SOURCES = {"project": ("project.hip", "predicate.h", "higs_internal.h"),
+                  "fill": ("emit.hip", "predicate.h", "higs_internal.h"),
+                  "sort": ("sort.hip", "higs_internal.h"),
+                  "raster": ("raster.hip", "raster_common.h", "higs_internal.h"),
+                  "seg_fill": ("segsort.hip", "predicate.h", "higs_internal.h"),
+                  "seg_sort": ("segsort.hip", "higs_internal.h")}
 
 
 def kernel_source_sha(kernel):
