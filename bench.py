@@ -326,10 +326,11 @@ def main():
     n = scene.n
     rl = {}
     seg = args.sort == "segmented"
-    # fill: reads the pair count of every gaussian (4 B) and the six binning
-    # fields and depth key of every visible one (28 B); writes a 12-B (key, id)
-    # pair, or in segmented mode one 8-B composite, per pair
-    fill_bytes = 4 * n + 28 * mean["visible"] + (8 if seg else 12) * mean["pairs"]
+    # fill: reads the pair count of every gaussian (4 B); onesweep mode: the
+    # macro-tile span word and depth key of every visible one (8 B), and writes
+    # a 12-B (key, id) pair per pair; segmented mode: the six binning fields
+    # and depth key of every visible one (28 B), and one 8-B composite per pair
+    fill_bytes = 4 * n + (28 if seg else 8) * mean["visible"] + (8 if seg else 12) * mean["pairs"]
     rl["fill"] = ("hbm", fill_bytes / (timers["fill"] * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", fill_bytes)
     proj_bytes = PROJECT_B_PER_GAUSSIAN * n + PROJECT_B_PER_VISIBLE * mean["visible"]
     rl["project"] = ("hbm", proj_bytes / (timers["project"] * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", proj_bytes)

@@ -149,9 +149,9 @@ fill_kernel(int64_t n, CamArgs cam, const float* __restrict__ f_mx, const float*
             const float* __restrict__ f_a, const float* __restrict__ f_b,
             const float* __restrict__ f_c, const float* __restrict__ f_tau,
             const uint32_t* __restrict__ f_key, const uint32_t* __restrict__ f_cnt,
-            const uint32_t* __restrict__ block_offsets, uint32_t max_pairs,
-            const DeviceCounters* __restrict__ dc, uint64_t* __restrict__ keys,
-            uint32_t* __restrict__ vals) {
+            const uint32_t* __restrict__ f_span, const uint32_t* __restrict__ block_offsets,
+            uint32_t max_pairs, const DeviceCounters* __restrict__ dc,
+            uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   __shared__ uint32_t wave_tot[kProjBlock / 64];
   const int64_t i = (int64_t)blockIdx.x * kProjBlock + threadIdx.x;
   const uint32_t cnt = i < n ? f_cnt[i] : 0u;
@@ -164,35 +164,42 @@ fill_kernel(int64_t n, CamArgs cam, const float* __restrict__ f_mx, const float*
   for (int w = 0; w < wave; ++w) base += wave_tot[w];
   if (cnt == 0) return;
   uint32_t at = base + incl - cnt;
-  BinFields f;
-  f.mx = f_mx[i];
-  f.my = f_my[i];
-  f.a = f_a[i];
-  f.b = f_b[i];
-  f.c = f_c[i];
-  f.tau = f_tau[i];
   const uint32_t dmin = dc->key_min;
   const uint32_t dbits = depth_bits(dmin, dc->key_max);
   const uint64_t depth = (uint64_t)(f_key[i] - dmin);
   const uint32_t gid = (uint32_t)i;
-  visit_macro_tiles(f, cam.width, cam.height, cam.n_mt_x, cam.n_mt_y, [&](uint32_t mt) {
+  auto emit = [&](uint32_t mt) {
     if (at < max_pairs) {
       keys[at] = ((uint64_t)mt << dbits) | depth;
       vals[at] = gid;
     }
     ++at;
-  });
+  };
+  const uint32_t span = f_span[i];
+  if (span) {  // the list the projection recorded
+    visit_span(span, cam.n_mt_x, emit);
+  } else {  // a long list: the predicate again, on the same fields
+    BinFields f;
+    f.mx = f_mx[i];
+    f.my = f_my[i];
+    f.a = f_a[i];
+    f.b = f_b[i];
+    f.c = f_c[i];
+    f.tau = f_tau[i];
+    visit_macro_tiles(f, cam.width, cam.height, cam.n_mt_x, cam.n_mt_y, emit);
+  }
 }
 
 hipError_t launch_fill(int64_t n, CamArgs cam, const float* f_mx, const float* f_my,
                        const float* f_a, const float* f_b, const float* f_c, const float* f_tau,
-                       const uint32_t* f_key, const uint32_t* f_cnt, const uint32_t* block_offsets,
-                       uint32_t max_pairs, const DeviceCounters* dc, uint64_t* keys,
-                       uint32_t* vals, hipStream_t s) {
+                       const uint32_t* f_key, const uint32_t* f_cnt, const uint32_t* f_span,
+                       const uint32_t* block_offsets, uint32_t max_pairs,
+                       const DeviceCounters* dc, uint64_t* keys, uint32_t* vals, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((n + kProjBlock - 1) / kProjBlock);
   hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(kProjBlock), 0, s, n, cam, f_mx, f_my, f_a,
-                     f_b, f_c, f_tau, f_key, f_cnt, block_offsets, max_pairs, dc, keys, vals);
+                     f_b, f_c, f_tau, f_key, f_cnt, f_span, block_offsets, max_pairs, dc, keys,
+                     vals);
   return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ struct higs_ctx {
   float *f_mx = nullptr, *f_my = nullptr, *f_a = nullptr, *f_b = nullptr, *f_c = nullptr,
         *f_tau = nullptr;
   uint32_t *f_key = nullptr, *f_cnt = nullptr;
+  uint32_t* f_span = nullptr;  // compact macro-tile list of each visible gaussian
   RasterRecord* rec = nullptr;
   uint32_t* block_sums = nullptr;  // per projection block: pair count, visible count
   uint64_t* keys[2] = {nullptr, nullptr};
@@ -106,7 +107,7 @@ void free_events(higs_ctx* c) {
 }
 
 void free_all(higs_ctx* c) {
-  void* bufs[] = {c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau, c->f_key, c->f_cnt,
+  void* bufs[] = {c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau, c->f_key, c->f_cnt, c->f_span,
                   c->rec, c->block_sums, c->keys[0], c->keys[1], c->vals[0], c->vals[1],
                   c->dbg_keys, c->dbg_vals, c->hist, c->plan, c->status, c->mt_off,
                   c->batch_first, c->batch_tab, c->active, c->partials, c->dc,
@@ -233,6 +234,7 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
   rc |= dalloc(&c->f_tau, G);
   rc |= dalloc(&c->f_key, G);
   rc |= dalloc(&c->f_cnt, G);
+  rc |= dalloc(&c->f_span, G);
   rc |= dalloc(&c->rec, G);
   rc |= dalloc(&c->block_sums, 2 * nblk);
   rc |= dalloc(&c->keys[0], P);
@@ -286,7 +288,7 @@ int64_t higs_ctx_footprint(const higs_params* params, int64_t max_gaussians, int
   const int64_t tiles = (P + kSortTile - 1) / kSortTile;
   const int64_t mt = (int64_t)((max_width + kMtW - 1) / kMtW) * ((max_height + kMtH - 1) / kMtH);
   int64_t bytes = 0;
-  bytes += G * (6 * 4 + 2 * 4);                // binning fields, key, count
+  bytes += G * (6 * 4 + 3 * 4);                // binning fields, key, count, span
   bytes += G * (int64_t)sizeof(RasterRecord);  // raster records
   bytes += 2 * nblk * 4;                       // per-block sums
   bytes += P * (2 * 8 + 2 * 4);                // two key and two value buffers
@@ -388,7 +390,7 @@ int higs_project(higs_ctx* c, int64_t n, const float* means, const float* scales
     TimerScope ts(c, HIGS_TIMER_PROJECT, s);
     rc = hip_err(launch_project(n, means, scales, quats, opacities, sh, c->ca, c->pa, c->f_mx,
                                 c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau, c->f_key, c->f_cnt,
-                                c->rec, c->block_sums, c->dc, s));
+                                c->f_span, c->rec, c->block_sums, c->dc, s));
   }
   if (rc) return rc;
   c->stage = 1;
@@ -461,8 +463,8 @@ int higs_bin_sort(higs_ctx* c, void* stream) {
   {
     TimerScope ts(c, HIGS_TIMER_FILL, s);
     rc = hip_err(launch_fill(c->n, c->ca, c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau,
-                             c->f_key, c->f_cnt, c->block_sums, (uint32_t)c->max_pairs, c->dc,
-                             c->keys[0], c->vals[0], s));
+                             c->f_key, c->f_cnt, c->f_span, c->block_sums,
+                             (uint32_t)c->max_pairs, c->dc, c->keys[0], c->vals[0], s));
   }
   if (rc) return rc;
   rc = keep_pairs(c, s);

@@ -106,17 +106,18 @@ hipError_t launch_clear(DeviceCounters* dc, uint32_t* hist, int n_hist, uint32_t
 hipError_t launch_project(int64_t n, const float* means, const float* scales, const float* quats,
                           const float* opac, const float* sh, CamArgs cam, ParamArgs prm,
                           float* f_mx, float* f_my, float* f_a, float* f_b, float* f_c,
-                          float* f_tau, uint32_t* f_key, uint32_t* f_cnt, RasterRecord* rec,
-                          uint32_t* block_sums, DeviceCounters* dc, hipStream_t s);
+                          float* f_tau, uint32_t* f_key, uint32_t* f_cnt, uint32_t* f_span,
+                          RasterRecord* rec, uint32_t* block_sums, DeviceCounters* dc,
+                          hipStream_t s);
 
 hipError_t launch_scan(int64_t n, const uint32_t* cnt, uint32_t* block_sums, uint32_t max_pairs,
                        DeviceCounters* dc, hipStream_t s);
 
 hipError_t launch_fill(int64_t n, CamArgs cam, const float* f_mx, const float* f_my,
                        const float* f_a, const float* f_b, const float* f_c, const float* f_tau,
-                       const uint32_t* f_key, const uint32_t* f_cnt, const uint32_t* block_offsets,
-                       uint32_t max_pairs, const DeviceCounters* dc, uint64_t* keys,
-                       uint32_t* vals, hipStream_t s);
+                       const uint32_t* f_key, const uint32_t* f_cnt, const uint32_t* f_span,
+                       const uint32_t* block_offsets, uint32_t max_pairs,
+                       const DeviceCounters* dc, uint64_t* keys, uint32_t* vals, hipStream_t s);
 
 struct SortBuffers {
   uint64_t* keys[2];

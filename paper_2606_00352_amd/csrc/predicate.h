@@ -21,10 +21,12 @@ struct BinFields {
   float mx, my, a, b, c, tau;
 };
 
-// Visits every macro-tile id the ellipse meets, ascending; fn(mt) per hit.
+// Visits every macro-tile the ellipse meets, ascending (band j, then column
+// i); fn(j, i) per hit.
 template <class Fn>
-__device__ __forceinline__ uint32_t visit_macro_tiles(const BinFields& f, int width, int height,
-                                                      int n_mt_x, int n_mt_y, Fn&& fn) {
+__device__ __forceinline__ uint32_t visit_macro_tiles_ji(const BinFields& f, int width,
+                                                         int height, int n_mt_x, int n_mt_y,
+                                                         Fn&& fn) {
 #pragma clang fp contract(off)
   const double mx = f.mx, my = f.my, a = f.a, b = f.b, c = f.c, tau = f.tau;
   const double W = (double)width, H = (double)height;
@@ -67,11 +69,59 @@ __device__ __forceinline__ uint32_t visit_macro_tiles(const BinFields& f, int wi
     if (ilo < 0) ilo = 0;
     if (ihi > n_mt_x - 1) ihi = n_mt_x - 1;
     for (int i = ilo; i <= ihi; ++i) {
-      fn((uint32_t)(j * n_mt_x + i));
+      fn(j, i);
       ++cnt;
     }
   }
   return cnt;
+}
+
+// Visits every macro-tile id the ellipse meets, ascending; fn(mt) per hit.
+template <class Fn>
+__device__ __forceinline__ uint32_t visit_macro_tiles(const BinFields& f, int width, int height,
+                                                      int n_mt_x, int n_mt_y, Fn&& fn) {
+  return visit_macro_tiles_ji(f, width, height, n_mt_x, n_mt_y,
+                              [&](int j, int i) { fn((uint32_t)(j * n_mt_x + i)); });
+}
+
+// The same list in one 32-bit word when it is short: within a band the hits
+// are one run of columns, so a list of at most two consecutive bands with at
+// most 16 columns each (band < 256, column < 128) is
+//   bit 31 set | band << 23 | first column << 16 | (columns - 1) << 12
+//   | second band present << 11 | its first column << 4 | its columns - 1.
+// Other lists encode as 0 (recompute them).  The projection records the word
+// during its count; the fill expands it in the same order.
+struct SpanTracker {
+  int ja = -1, ia0 = 0, ia1 = 0, jb = -1, ib0 = 0, ib1 = 0;
+  bool ok = true;
+  __device__ __forceinline__ void add(int j, int i) {
+    if (j == ja) ia1 = i;
+    else if (ja < 0) ja = j, ia0 = ia1 = i;
+    else if (j == jb) ib1 = i;
+    else if (jb < 0 && j == ja + 1) jb = j, ib0 = ib1 = i;
+    else ok = false;
+  }
+  __device__ __forceinline__ uint32_t encode() const {
+    if (!ok || ja < 0 || ja > 255 || ia0 > 127 || ia1 - ia0 > 15) return 0u;
+    uint32_t w = 0x80000000u | ((uint32_t)ja << 23) | ((uint32_t)ia0 << 16) |
+                 ((uint32_t)(ia1 - ia0) << 12);
+    if (jb >= 0) {
+      if (ib0 > 127 || ib1 - ib0 > 15) return 0u;
+      w |= 0x800u | ((uint32_t)ib0 << 4) | (uint32_t)(ib1 - ib0);
+    }
+    return w;
+  }
+};
+
+// fn(mt) for every macro-tile of a nonzero span word, in visit order.
+template <class Fn>
+__device__ __forceinline__ void visit_span(uint32_t w, int n_mt_x, Fn&& fn) {
+  const uint32_t ja = (w >> 23) & 255u, ia0 = (w >> 16) & 127u, la = (w >> 12) & 15u;
+  for (uint32_t i = 0; i <= la; ++i) fn(ja * (uint32_t)n_mt_x + ia0 + i);
+  if (w & 0x800u) {
+    const uint32_t ib0 = (w >> 4) & 127u, lb = w & 15u;
+    for (uint32_t i = 0; i <= lb; ++i) fn((ja + 1u) * (uint32_t)n_mt_x + ib0 + i);
+  }
 }
 
 }  // namespace higs

@@ -13,7 +13,9 @@
 // gaussians into the frame's [min, max] (used to compress the sort keys).
 //
 // Outputs: SoA binning fields (coalesced), a 48-byte raster record per
-// visible gaussian, per-gaussian pair counts and per-block count sums.
+// visible gaussian, per-gaussian pair counts, the compact form of each visible
+// gaussian's macro-tile list (predicate.h, SpanTracker) and per-block count
+// sums.
 #include "higs_internal.h"
 #include "predicate.h"
 
@@ -176,8 +178,8 @@ project_kernel(int64_t n, const float* __restrict__ means, const float* __restri
                float* __restrict__ f_mx, float* __restrict__ f_my, float* __restrict__ f_a,
                float* __restrict__ f_b, float* __restrict__ f_c, float* __restrict__ f_tau,
                uint32_t* __restrict__ f_key, uint32_t* __restrict__ f_cnt,
-               RasterRecord* __restrict__ rec, uint32_t* __restrict__ block_sums,
-               DeviceCounters* __restrict__ dc, bool sh_vec4) {
+               uint32_t* __restrict__ f_span, RasterRecord* __restrict__ rec,
+               uint32_t* __restrict__ block_sums, DeviceCounters* __restrict__ dc, bool sh_vec4) {
   __shared__ uint32_t wave_min[kProjBlock / 64], wave_max[kProjBlock / 64];
   __shared__ uint32_t wave_sums[2][kProjBlock / 64];
   const int64_t i = (int64_t)blockIdx.x * kProjBlock + threadIdx.x;
@@ -210,7 +212,10 @@ project_kernel(int64_t n, const float* __restrict__ means, const float* __restri
       f.tau = (float)g.tau;
       const float tzf = (float)g.tz;
       key = __float_as_uint(tzf);
-      cnt = visit_macro_tiles(f, cam.width, cam.height, cam.n_mt_x, cam.n_mt_y, [](uint32_t) {});
+      SpanTracker span;
+      cnt = visit_macro_tiles_ji(f, cam.width, cam.height, cam.n_mt_x, cam.n_mt_y,
+                                 [&](int j, int ic) { span.add(j, ic); });
+      if (cnt > 0) f_span[i] = span.encode();
       f_mx[i] = f.mx;
       f_my[i] = f.my;
       f_a[i] = f.a;
@@ -309,8 +314,9 @@ project_kernel(int64_t n, const float* __restrict__ means, const float* __restri
 hipError_t launch_project(int64_t n, const float* means, const float* scales, const float* quats,
                           const float* opac, const float* sh, CamArgs cam, ParamArgs prm,
                           float* f_mx, float* f_my, float* f_a, float* f_b, float* f_c,
-                          float* f_tau, uint32_t* f_key, uint32_t* f_cnt, RasterRecord* rec,
-                          uint32_t* block_sums, DeviceCounters* dc, hipStream_t s) {
+                          float* f_tau, uint32_t* f_key, uint32_t* f_cnt, uint32_t* f_span,
+                          RasterRecord* rec, uint32_t* block_sums, DeviceCounters* dc,
+                          hipStream_t s) {
   if (n <= 0) return hipSuccess;
   // camera centre, -R^T t, for the SH view direction
   float3 campos;
@@ -320,7 +326,7 @@ hipError_t launch_project(int64_t n, const float* means, const float* scales, co
   const unsigned blocks = (unsigned)((n + kProjBlock - 1) / kProjBlock);
   hipLaunchKernelGGL(project_kernel, dim3(blocks), dim3(kProjBlock), 0, s, n, means, scales,
                      quats, opac, sh, cam, prm, campos, f_mx, f_my,
-                     f_a, f_b, f_c, f_tau, f_key, f_cnt, rec, block_sums, dc,
+                     f_a, f_b, f_c, f_tau, f_key, f_cnt, f_span, rec, block_sums, dc,
                      (reinterpret_cast<uintptr_t>(sh) & 15u) == 0);
   return hipGetLastError();
 }
