@@ -480,7 +480,8 @@ int higs_bin_sort(higs_ctx* c, void* stream) {
   sb.max_tiles = c->max_tiles;
   {
     TimerScope ts(c, HIGS_TIMER_SORT, s);
-    rc = hip_err(launch_sort(c->n_passes, c->epoch, sb, c->dc, c->n_cus, s));
+    rc = hip_err(launch_sort(c->n_passes, n_bits((uint32_t)(c->n_mt - 1)), c->epoch, sb, c->dc,
+                             c->n_cus, s));
   }
   c->epoch += (uint32_t)c->n_passes;
   if (c->epoch >= (1u << 30) - 64) c->epoch = 1;  // status words hold 30 epoch bits

@@ -128,8 +128,8 @@ struct SortBuffers {
   uint64_t* status;      // [max_tiles][kRadix] look-back words
   uint32_t max_tiles;
 };
-hipError_t launch_sort(int n_passes, uint32_t epoch_base, SortBuffers sb, DeviceCounters* dc,
-                       int n_cus, hipStream_t s);
+hipError_t launch_sort(int n_passes, int mt_bits, uint32_t epoch_base, SortBuffers sb,
+                       DeviceCounters* dc, int n_cus, hipStream_t s);
 
 hipError_t launch_batch(int n_mt, uint32_t batch_cap, uint32_t max_batches, const uint64_t* const* keys2,
                         DeviceCounters* dc, uint32_t* mt_off, uint32_t* batch_first,

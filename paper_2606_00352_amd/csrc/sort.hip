@@ -40,7 +40,7 @@ constexpr int kHistCopies = 8;  // LDS copies: lanes l and l+8k share one, 8-way
 constexpr int kHistBatch = 8;   // keys loaded together per thread
 __global__ void __launch_bounds__(kHistThreads)
 sort_hist_kernel(const uint64_t* __restrict__ keys, const DeviceCounters* __restrict__ dc,
-                 int n_passes, uint32_t* __restrict__ hist) {
+                 int n_passes, int mt_bits, uint32_t* __restrict__ hist) {
   // the top digits of a frame's keys take few values: spreading the counters
   // over copies keeps the LDS atomics of one wave from piling on one address
   __shared__ uint32_t h[kHistCopies][kMaxPasses * kRadix];
@@ -48,6 +48,9 @@ sort_hist_kernel(const uint64_t* __restrict__ keys, const DeviceCounters* __rest
     (&h[0][0])[k] = 0;
   __syncthreads();
   const uint32_t n = dc->n_pairs;
+  // digit positions above the frame's key width are zero in every key
+  const int np = min(n_passes, (mt_bits + (int)depth_bits(dc->key_min, dc->key_max) +
+                                kRadixBits - 1) / kRadixBits);
   uint32_t* mine = h[threadIdx.x & (kHistCopies - 1)];
   // kHistBatch independent loads in flight per thread, then their counts
   const uint32_t stride = gridDim.x * kHistThreads;
@@ -61,7 +64,7 @@ sort_hist_kernel(const uint64_t* __restrict__ keys, const DeviceCounters* __rest
 #pragma unroll
     for (int b = 0; b < kHistBatch; ++b) {
       if (i0 + (uint32_t)b * stride >= n) break;
-      for (int p = 0; p < n_passes; ++p)
+      for (int p = 0; p < np; ++p)
         atomicAdd(&mine[p * kRadix + (uint32_t)((key[b] >> (kRadixBits * p)) & (kRadix - 1))], 1u);
     }
   }
@@ -78,14 +81,16 @@ sort_hist_kernel(const uint64_t* __restrict__ keys, const DeviceCounters* __rest
 // buffer and the exclusive digit bases.
 __global__ void __launch_bounds__(kRadix)
 sort_plan_kernel(const uint32_t* __restrict__ hist, DeviceCounters* __restrict__ dc, int n_passes,
-                 uint32_t* __restrict__ plan, uint32_t* __restrict__ base) {
+                 int mt_bits, uint32_t* __restrict__ plan, uint32_t* __restrict__ base) {
   __shared__ uint32_t wave_tot[kRadix / 64];
   const uint32_t n = dc->n_pairs;
+  const int np = (mt_bits + (int)depth_bits(dc->key_min, dc->key_max) + kRadixBits - 1) / kRadixBits;
   const int d = threadIdx.x, lane = d & 63, wave = d >> 6;
   uint32_t cur = 0, moved = 0;
   for (int p = 0; p < n_passes; ++p) {
     const uint32_t c = hist[p * kRadix + d];
-    const int trivial = __syncthreads_or(c == n);
+    // a pass above the key width, or one whose digit every key shares
+    const int trivial = __syncthreads_or(c == n) || p >= np;
     // exclusive scan of the 256 digit counts
     uint32_t v = c;
 #pragma unroll
@@ -276,8 +281,8 @@ onesweep_kernel(int pass, uint32_t epoch, uint64_t* __restrict__ k0, uint32_t* _
 
 static int g_onesweep_per_cu = 0;
 
-hipError_t launch_sort(int n_passes, uint32_t epoch_base, SortBuffers sb, DeviceCounters* dc,
-                       int n_cus, hipStream_t s) {
+hipError_t launch_sort(int n_passes, int mt_bits, uint32_t epoch_base, SortBuffers sb,
+                       DeviceCounters* dc, int n_cus, hipStream_t s) {
   if (g_onesweep_per_cu == 0) {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, onesweep_kernel, kSortThreads, 0) !=
@@ -287,9 +292,9 @@ hipError_t launch_sort(int n_passes, uint32_t epoch_base, SortBuffers sb, Device
     g_onesweep_per_cu = nb;
   }
   hipLaunchKernelGGL(sort_hist_kernel, dim3(n_cus * 4), dim3(kHistThreads), 0, s, sb.keys[0], dc,
-                     n_passes, sb.hist);
-  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(kRadix), 0, s, sb.hist, dc, n_passes, sb.plan,
-                     sb.plan + kMaxPasses);
+                     n_passes, mt_bits, sb.hist);
+  hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(kRadix), 0, s, sb.hist, dc, n_passes, mt_bits,
+                     sb.plan, sb.plan + kMaxPasses);
   const int workers = n_cus * g_onesweep_per_cu;
   for (int p = 0; p < n_passes; ++p) {
     hipLaunchKernelGGL(onesweep_kernel, dim3(workers), dim3(kSortThreads), 0, s, p,
