@@ -144,6 +144,11 @@ hipError_t launch_scan(int64_t n, const uint32_t* cnt, uint32_t* block_sums, uin
   return hipGetLastError();
 }
 
+// One workgroup per kFillBlocks consecutive projection blocks (256 gaussians
+// each, one per thread per block): every count, span word and depth key of
+// the group is loaded first, then each block's pairs are written at its scan
+// offset plus the wave prefix sums.
+constexpr int kFillBlocks = 4;
 __global__ void __launch_bounds__(kProjBlock)
 fill_kernel(int64_t n, CamArgs cam, const float* __restrict__ f_mx, const float* __restrict__ f_my,
             const float* __restrict__ f_a, const float* __restrict__ f_b,
@@ -152,41 +157,57 @@ fill_kernel(int64_t n, CamArgs cam, const float* __restrict__ f_mx, const float*
             const uint32_t* __restrict__ f_span, const uint32_t* __restrict__ block_offsets,
             uint32_t max_pairs, const DeviceCounters* __restrict__ dc,
             uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  __shared__ uint32_t wave_tot[kProjBlock / 64];
-  const int64_t i = (int64_t)blockIdx.x * kProjBlock + threadIdx.x;
-  const uint32_t cnt = i < n ? f_cnt[i] : 0u;
-  const uint32_t incl = wave_incl_scan(cnt);
+  __shared__ uint32_t wave_tot[kFillBlocks][kProjBlock / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 63) wave_tot[wave] = incl;
+  const int64_t blk0 = (int64_t)blockIdx.x * kFillBlocks;
+  uint32_t cnt[kFillBlocks], span[kFillBlocks], key[kFillBlocks], incl[kFillBlocks];
+#pragma unroll
+  for (int k = 0; k < kFillBlocks; ++k) {
+    const int64_t i = (blk0 + k) * kProjBlock + threadIdx.x;
+    const bool in = i < n;
+    cnt[k] = in ? f_cnt[i] : 0u;
+    span[k] = in ? f_span[i] : 0u;
+    key[k] = in ? f_key[i] : 0u;
+  }
+  const int64_t n_blocks = (n + kProjBlock - 1) / kProjBlock;
+  uint32_t boff[kFillBlocks];
+#pragma unroll
+  for (int k = 0; k < kFillBlocks; ++k) {
+    boff[k] = blk0 + k < n_blocks ? block_offsets[2 * (blk0 + k)] : 0u;
+    incl[k] = wave_incl_scan(cnt[k]);
+    if (lane == 63) wave_tot[k][wave] = incl[k];
+  }
   __syncthreads();
-  if (__ballot(cnt > 0) == 0) return;  // whole wave invisible
-  uint32_t base = block_offsets[2 * blockIdx.x];
-  for (int w = 0; w < wave; ++w) base += wave_tot[w];
-  if (cnt == 0) return;
-  uint32_t at = base + incl - cnt;
   const uint32_t dmin = dc->key_min;
   const uint32_t dbits = depth_bits(dmin, dc->key_max);
-  const uint64_t depth = (uint64_t)(f_key[i] - dmin);
-  const uint32_t gid = (uint32_t)i;
-  auto emit = [&](uint32_t mt) {
-    if (at < max_pairs) {
-      keys[at] = ((uint64_t)mt << dbits) | depth;
-      vals[at] = gid;
+#pragma unroll
+  for (int k = 0; k < kFillBlocks; ++k) {
+    if (__ballot(cnt[k] > 0) == 0) continue;  // whole wave invisible in this block
+    uint32_t at = boff[k] + incl[k] - cnt[k];
+    for (int w = 0; w < wave; ++w) at += wave_tot[k][w];
+    if (cnt[k] == 0) continue;
+    const int64_t i = (blk0 + k) * kProjBlock + threadIdx.x;
+    const uint64_t depth = (uint64_t)(key[k] - dmin);
+    const uint32_t gid = (uint32_t)i;
+    auto emit = [&](uint32_t mt) {
+      if (at < max_pairs) {
+        keys[at] = ((uint64_t)mt << dbits) | depth;
+        vals[at] = gid;
+      }
+      ++at;
+    };
+    if (span[k]) {  // the list the projection recorded
+      visit_span(span[k], cam.n_mt_x, emit);
+    } else {  // a long list: the predicate again, on the same fields
+      BinFields f;
+      f.mx = f_mx[i];
+      f.my = f_my[i];
+      f.a = f_a[i];
+      f.b = f_b[i];
+      f.c = f_c[i];
+      f.tau = f_tau[i];
+      visit_macro_tiles(f, cam.width, cam.height, cam.n_mt_x, cam.n_mt_y, emit);
     }
-    ++at;
-  };
-  const uint32_t span = f_span[i];
-  if (span) {  // the list the projection recorded
-    visit_span(span, cam.n_mt_x, emit);
-  } else {  // a long list: the predicate again, on the same fields
-    BinFields f;
-    f.mx = f_mx[i];
-    f.my = f_my[i];
-    f.a = f_a[i];
-    f.b = f_b[i];
-    f.c = f_c[i];
-    f.tau = f_tau[i];
-    visit_macro_tiles(f, cam.width, cam.height, cam.n_mt_x, cam.n_mt_y, emit);
   }
 }
 
@@ -196,7 +217,8 @@ hipError_t launch_fill(int64_t n, CamArgs cam, const float* f_mx, const float* f
                        const uint32_t* block_offsets, uint32_t max_pairs,
                        const DeviceCounters* dc, uint64_t* keys, uint32_t* vals, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((n + kProjBlock - 1) / kProjBlock);
+  const int64_t n_blocks = (n + kProjBlock - 1) / kProjBlock;
+  const unsigned blocks = (unsigned)((n_blocks + kFillBlocks - 1) / kFillBlocks);
   hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(kProjBlock), 0, s, n, cam, f_mx, f_my, f_a,
                      f_b, f_c, f_tau, f_key, f_cnt, f_span, block_offsets, max_pairs, dc, keys,
                      vals);

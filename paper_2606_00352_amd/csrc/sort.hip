@@ -36,7 +36,7 @@ __device__ __forceinline__ uint64_t status_word(uint32_t epoch, uint32_t flag, u
 }
 
 constexpr int kHistThreads = 256;
-constexpr int kHistCopies = 8;  // LDS copies: lanes l and l+8k share one, 8-way at worst
+constexpr int kHistCopies = 4;  // LDS copies: lanes l and l+4k share one, 16-way at worst
 constexpr int kHistBatch = 8;   // keys loaded together per thread
 __global__ void __launch_bounds__(kHistThreads)
 sort_hist_kernel(const uint64_t* __restrict__ keys, const DeviceCounters* __restrict__ dc,
@@ -44,13 +44,13 @@ sort_hist_kernel(const uint64_t* __restrict__ keys, const DeviceCounters* __rest
   // the top digits of a frame's keys take few values: spreading the counters
   // over copies keeps the LDS atomics of one wave from piling on one address
   __shared__ uint32_t h[kHistCopies][kMaxPasses * kRadix];
-  for (int k = threadIdx.x; k < kHistCopies * kMaxPasses * kRadix; k += kHistThreads)
-    (&h[0][0])[k] = 0;
-  __syncthreads();
   const uint32_t n = dc->n_pairs;
   // digit positions above the frame's key width are zero in every key
   const int np = min(n_passes, (mt_bits + (int)depth_bits(dc->key_min, dc->key_max) +
                                 kRadixBits - 1) / kRadixBits);
+  for (int c = 0; c < kHistCopies; ++c)
+    for (int k = threadIdx.x; k < np * kRadix; k += kHistThreads) h[c][k] = 0;
+  __syncthreads();
   uint32_t* mine = h[threadIdx.x & (kHistCopies - 1)];
   // kHistBatch independent loads in flight per thread, then their counts
   const uint32_t stride = gridDim.x * kHistThreads;
@@ -69,7 +69,7 @@ sort_hist_kernel(const uint64_t* __restrict__ keys, const DeviceCounters* __rest
     }
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < n_passes * kRadix; k += kHistThreads) {
+  for (int k = threadIdx.x; k < np * kRadix; k += kHistThreads) {
     uint32_t v = 0;
 #pragma unroll
     for (int c = 0; c < kHistCopies; ++c) v += h[c][k];
@@ -291,7 +291,7 @@ hipError_t launch_sort(int n_passes, int mt_bits, uint32_t epoch_base, SortBuffe
       nb = 1;
     g_onesweep_per_cu = nb;
   }
-  hipLaunchKernelGGL(sort_hist_kernel, dim3(n_cus * 4), dim3(kHistThreads), 0, s, sb.keys[0], dc,
+  hipLaunchKernelGGL(sort_hist_kernel, dim3(n_cus * 2), dim3(kHistThreads), 0, s, sb.keys[0], dc,
                      n_passes, mt_bits, sb.hist);
   hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(kRadix), 0, s, sb.hist, dc, n_passes, mt_bits,
                      sb.plan, sb.plan + kMaxPasses);
