@@ -217,9 +217,10 @@ raster_backward_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ 
               d5 = dal * (ev.e / B.y);  // d alpha / d o = exp(-q/2); o > 0 for a listed gaussian
               const float dq = -dal * ev.al * kLn2f;  // dL/dq'
               const float du = 2.0f * ev.u * dq, dv = 2.0f * ev.v * dq;
-              d2 = du * ev.dx;
-              d3 = du * ev.dy;
-              d4 = dv * ev.dy;
+              const float dx = pxr - C.z, dy = pyr - C.w;  // pixel minus centre
+              d2 = du * dx;
+              d3 = du * dy;
+              d4 = dv * dy;
               d0 = -du * A.z;
               d1 = -(du * A.w + dv * B.x);
             }

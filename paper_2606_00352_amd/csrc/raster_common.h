@@ -14,9 +14,9 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 struct RasterLds {
-  float4 ga[kMaxBatch];  // mx, my (macro-tile relative), l0', l1'
+  float4 ga[kMaxBatch];  // c0 = l0' mx + l1' my, c1 = l2' my, l0', l1' (mx, my macro-tile relative)
   float4 gb[kMaxBatch];  // l2', o, r, g
-  float4 gc[kMaxBatch];  // b, log2 o, -, - (the stride of ga and gb: one address for all three reads)
+  float4 gc[kMaxBatch];  // b, log2 o, mx, my (the stride of ga and gb: one address for all reads)
   uint64_t masks[kMiniBatches][kTilesPerMt];
   uint32_t queue[kTilesPerMt];
   uint32_t qcount;
@@ -65,19 +65,19 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
 
 // alpha = min(alpha_max, o exp(-q/2)) at the pixel centre (pxr, pyr)
 // relative to the macro-tile, from the prescaled factors in LDS:
-// q' = (l0' dx + l1' dy)^2 + (l2' dy)^2 = q log2(e)/2, and with the stored
-// lo = log2(o), o exp(-q/2) = exp2(lo - q') (the opacity rides in the
-// exponent: no multiply).  e is that unclamped alpha.
+// q' = u^2 + v^2 = q log2(e)/2 with u = l0' dx + l1' dy, v = l2' dy, formed as
+// u = l0' pxr + l1' pyr - c0 and v = l2' pyr - c1 (three fused multiply-adds
+// per pixel, no differences), and with the stored lo = log2(o),
+// o exp(-q/2) = exp2(lo - q') (the opacity rides in the exponent).  e is that
+// unclamped alpha.
 struct PixelEval {
-  float dx, dy, u, v, e, al;
+  float u, v, e, al;
 };
 __device__ __forceinline__ PixelEval eval_alpha(const float4& A, const float4& B, float lo,
                                                 float pxr, float pyr, float amax) {
   PixelEval r;
-  r.dx = pxr - A.x;
-  r.dy = pyr - A.y;
-  r.u = A.z * r.dx + A.w * r.dy;
-  r.v = B.x * r.dy;
+  r.u = fmaf(A.z, pxr, fmaf(A.w, pyr, -A.x));
+  r.v = fmaf(B.x, pyr, -A.y);
   r.e = __builtin_amdgcn_exp2f(fmaf(-r.u, r.u, fmaf(-r.v, r.v, lo)));
   r.al = fminf(amax, r.e);
   return r;
@@ -123,9 +123,11 @@ __device__ __forceinline__ uint32_t stage_unit(RasterLds& L, const UnitInfo& I,
       const float4* rp = reinterpret_cast<const float4*>(rec + gid);
       const float4 A = rp[0], B = rp[1], C = rp[2];
       const float mxr = A.x - (float)I.x0, myr = A.y - (float)I.y0;
-      L.ga[j] = make_float4(mxr, myr, A.z * kSqrtHalfLog2e, A.w * kSqrtHalfLog2e);
-      L.gb[j] = make_float4(B.x * kSqrtHalfLog2e, B.y, B.z, B.w);
-      L.gc[j] = make_float4(C.x, __builtin_amdgcn_logf(B.y), 0.0f, 0.0f);  // b, log2 o
+      const float l0k = A.z * kSqrtHalfLog2e, l1k = A.w * kSqrtHalfLog2e;
+      const float l2k = B.x * kSqrtHalfLog2e;
+      L.ga[j] = make_float4(fmaf(l0k, mxr, l1k * myr), l2k * myr, l0k, l1k);
+      L.gb[j] = make_float4(l2k, B.y, B.z, B.w);
+      L.gc[j] = make_float4(C.x, __builtin_amdgcn_logf(B.y), mxr, myr);  // b, log2 o, centre
       tmask = tile_overlap(mxr, myr, A.z, A.w, B.x, C.y, I.tiles_x, I.tiles_y);
     }
     uint64_t mine = 0;
