@@ -24,11 +24,12 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # lane-instructions/s: 256 CUs x 
 # Algorithmic bytes per unit (what each kernel must move):
 #   project: reads means+scales+quats+opacity 44 B per gaussian and 192 B of SH
 #            per visible gaussian; writes depth key + count 8 B per gaussian and
-#            binning fields 24 B + raster record 48 B per visible gaussian.
+#            binning fields 24 B + span word 4 B + raster record 48 B per visible
+#            gaussian.
 #   sort:    histogram read 8 B per pair, then per executed pass 12 B read +
 #            12 B written per pair.
 PROJECT_B_PER_GAUSSIAN = 44 + 8
-PROJECT_B_PER_VISIBLE = 192 + 24 + 48
+PROJECT_B_PER_VISIBLE = 192 + 24 + 4 + 48
 # Arithmetic operations per pixel-gaussian evaluation of the raster inner loop
 # (dx, dy, two for u, v, two for q, exp2, opacity product, clamp, threshold
 # test, weight, three colour FMAs, transmittance update).
@@ -48,14 +49,14 @@ COPY_CALIBRATION_BYTES = 1 << 30
 MEASURED_TRAFFIC = {
     # profiles/frame_1080p_5p8m_hbm_traffic.md (sort: histogram + plan + every
     # onesweep dispatch of a frame)
-    "raster": {"src_sha256": "dda52f6a55eb7dd9a762be6ac3d9644973bd49dbd7cebb3be110740510d885b5",
-              "bytes_per_launch": 1513916906},
-    "project": {"src_sha256": "38cfb7009ccec5dcb9e24eb670cdaee7fd376ebebe7a5eb9afe8437934083c69",
-               "bytes_per_launch": 1830514020},
-    "fill": {"src_sha256": "5492682a75452826d7e5db1868ff98257f2bc0d942d59a1e2cde127048d94106",
-            "bytes_per_launch": 284277185},
-    "sort": {"src_sha256": "fccd3bfba2e534f9e8426384a2e7e5aa50a3123382e3740895468ae2fe3fb5a7",
-            "bytes_per_launch": 1175243839},
+    "raster": {"src_sha256": "52f8d825e4cbdff496301c5115d017a477d11e72d83d5f30d7a13b05f7d7ba92",
+              "bytes_per_launch": 1514091113},
+    "project": {"src_sha256": "6d885e23504217b902497b8cebe99e1eebf4b706e7baf4cc0c0b74a42434ce63",
+               "bytes_per_launch": 1853978704},
+    "fill": {"src_sha256": "98ed87a5d120a8f0774c82de844185f31b63a83bc2416c056f459b5aa0788209",
+            "bytes_per_launch": 166149043},
+    "sort": {"src_sha256": "bd15a88f02773ae0b9f0ae82ff124eced46ce979cd15bbf2ba1b0c1d21c5c0cb",
+            "bytes_per_launch": 1174016785},
 }
 # the sources each figure depends on (the shared header holds the kernels' shapes)
 KERNEL_SOURCES = {"project": ("project.hip", "predicate.h", "higs_internal.h"),
