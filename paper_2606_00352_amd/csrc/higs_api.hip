@@ -434,14 +434,15 @@ int higs_bin_sort(higs_ctx* c, void* stream) {
     {
       TimerScope ts(c, HIGS_TIMER_SCAN, s);
       rc = hip_err(launch_seg_count(c->n, c->ca, c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c,
-                                    c->f_tau, c->f_cnt, sb, (uint32_t)c->max_pairs, c->dc, s));
+                                    c->f_tau, c->f_cnt, c->f_span, sb, (uint32_t)c->max_pairs,
+                                    c->dc, s));
     }
     if (rc) return rc;
     {
       TimerScope ts(c, HIGS_TIMER_FILL, s);
       rc = hip_err(launch_seg_fill(c->n, c->ca, c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c,
-                                   c->f_tau, c->f_key, c->f_cnt, sb, (uint32_t)c->max_pairs,
-                                   c->dc, s));
+                                   c->f_tau, c->f_key, c->f_cnt, c->f_span, sb,
+                                   (uint32_t)c->max_pairs, c->dc, s));
     }
     if (rc) return rc;
     rc = keep_pairs(c, s);

@@ -170,12 +170,12 @@ struct SegBuffers {
 // of composites; then the sort of every segment (chunk sort, merge levels).
 hipError_t launch_seg_count(int64_t n, CamArgs cam, const float* f_mx, const float* f_my,
                             const float* f_a, const float* f_b, const float* f_c,
-                            const float* f_tau, const uint32_t* f_cnt, SegBuffers sb,
-                            uint32_t max_pairs, DeviceCounters* dc, hipStream_t s);
+                            const float* f_tau, const uint32_t* f_cnt, const uint32_t* f_span,
+                            SegBuffers sb, uint32_t max_pairs, DeviceCounters* dc, hipStream_t s);
 hipError_t launch_seg_fill(int64_t n, CamArgs cam, const float* f_mx, const float* f_my,
                            const float* f_a, const float* f_b, const float* f_c, const float* f_tau,
-                           const uint32_t* f_key, const uint32_t* f_cnt, SegBuffers sb,
-                           uint32_t max_pairs, DeviceCounters* dc, hipStream_t s);
+                           const uint32_t* f_key, const uint32_t* f_cnt, const uint32_t* f_span,
+                           SegBuffers sb, uint32_t max_pairs, DeviceCounters* dc, hipStream_t s);
 hipError_t launch_seg_sort(int64_t n, int n_mt, SegBuffers sb, uint32_t max_pairs,
                            DeviceCounters* dc, int n_cus, hipStream_t s);
 

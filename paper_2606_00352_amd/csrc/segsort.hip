@@ -5,9 +5,10 @@
 //
 // seg_count_kernel (one workgroup per partition batch of B_p = 8,192
 //   gaussians): an LDS histogram with one counter per macro-tile, filled by LDS
-//   atomics from each visible gaussian's macro-tile list (the exact predicate
-//   on the stored float32 fields), then added to the frame's per-macro-tile
-//   totals (one global atomic per touched counter).
+//   atomics from each visible gaussian's macro-tile list (the compact list the
+//   projection recorded, else the exact predicate again on the stored float32
+//   fields), then added to the frame's per-macro-tile totals (one global
+//   atomic per touched counter).
 // seg_scan_kernel (one workgroup): segment offsets (exclusive scan of the
 //   totals), the fill cursors, the pair total and overflow, the chunk table
 //   of the segment sort and the block table of its merges.
@@ -43,7 +44,8 @@ seg_count_kernel(int64_t n, CamArgs cam, int n_mt, const float* __restrict__ f_m
                  const float* __restrict__ f_my, const float* __restrict__ f_a,
                  const float* __restrict__ f_b, const float* __restrict__ f_c,
                  const float* __restrict__ f_tau, const uint32_t* __restrict__ f_cnt,
-                 uint32_t* __restrict__ seg_count, DeviceCounters* __restrict__ dc) {
+                 const uint32_t* __restrict__ f_span, uint32_t* __restrict__ seg_count,
+                 DeviceCounters* __restrict__ dc) {
   HIP_DYNAMIC_SHARED(uint32_t, hist)
   __shared__ uint32_t s_vis;
   for (int m = threadIdx.x; m < n_mt; m += kSegThreads) hist[m] = 0;
@@ -55,15 +57,20 @@ seg_count_kernel(int64_t n, CamArgs cam, int n_mt, const float* __restrict__ f_m
     const int64_t i = base + (int64_t)r * kSegThreads + threadIdx.x;
     if (i >= n || f_cnt[i] == 0) continue;
     ++vis;
-    BinFields f;
-    f.mx = f_mx[i];
-    f.my = f_my[i];
-    f.a = f_a[i];
-    f.b = f_b[i];
-    f.c = f_c[i];
-    f.tau = f_tau[i];
-    visit_macro_tiles(f, cam.width, cam.height, cam.n_mt_x, cam.n_mt_y,
-                      [&](uint32_t mt) { atomicAdd(&hist[mt], 1u); });
+    auto hit = [&](uint32_t mt) { atomicAdd(&hist[mt], 1u); };
+    const uint32_t w = f_span[i];
+    if (w) {
+      visit_span(w, cam.n_mt_x, hit);
+    } else {
+      BinFields f;
+      f.mx = f_mx[i];
+      f.my = f_my[i];
+      f.a = f_a[i];
+      f.b = f_b[i];
+      f.c = f_c[i];
+      f.tau = f_tau[i];
+      visit_macro_tiles(f, cam.width, cam.height, cam.n_mt_x, cam.n_mt_y, hit);
+    }
   }
   if (vis) atomicAdd(&s_vis, vis);
   __syncthreads();
@@ -152,7 +159,8 @@ seg_fill_kernel(int64_t n, CamArgs cam, int n_mt, uint32_t gbits, const float* _
                 const float* __restrict__ f_my, const float* __restrict__ f_a,
                 const float* __restrict__ f_b, const float* __restrict__ f_c,
                 const float* __restrict__ f_tau, const uint32_t* __restrict__ f_key,
-                const uint32_t* __restrict__ f_cnt, uint32_t* __restrict__ cursor,
+                const uint32_t* __restrict__ f_cnt, const uint32_t* __restrict__ f_span,
+                uint32_t* __restrict__ cursor,
                 const DeviceCounters* __restrict__ dc, uint32_t max_pairs,
                 uint64_t* __restrict__ comp) {
   HIP_DYNAMIC_SHARED(uint32_t, lds)
@@ -161,21 +169,26 @@ seg_fill_kernel(int64_t n, CamArgs cam, int n_mt, uint32_t gbits, const float* _
   for (int m = threadIdx.x; m < n_mt; m += kSegThreads) cnt[m] = 0;
   __syncthreads();
   const int64_t b0 = (int64_t)blockIdx.x * kSegBatch;
-  auto fields = [&](int64_t i) {
-    BinFields f;
-    f.mx = f_mx[i];
-    f.my = f_my[i];
-    f.a = f_a[i];
-    f.b = f_b[i];
-    f.c = f_c[i];
-    f.tau = f_tau[i];
-    return f;
+  // each gaussian's macro-tile list: the recorded span, else the predicate
+  auto visit = [&](int64_t i, auto&& fn) {
+    const uint32_t w = f_span[i];
+    if (w) {
+      visit_span(w, cam.n_mt_x, fn);
+    } else {
+      BinFields f;
+      f.mx = f_mx[i];
+      f.my = f_my[i];
+      f.a = f_a[i];
+      f.b = f_b[i];
+      f.c = f_c[i];
+      f.tau = f_tau[i];
+      visit_macro_tiles(f, cam.width, cam.height, cam.n_mt_x, cam.n_mt_y, fn);
+    }
   };
   for (int r = 0; r < kSegPerThread; ++r) {
     const int64_t i = b0 + (int64_t)r * kSegThreads + threadIdx.x;
     if (i >= n || f_cnt[i] == 0) continue;
-    visit_macro_tiles(fields(i), cam.width, cam.height, cam.n_mt_x, cam.n_mt_y,
-                      [&](uint32_t mt) { atomicAdd(&cnt[mt], 1u); });
+    visit(i, [&](uint32_t mt) { atomicAdd(&cnt[mt], 1u); });
   }
   __syncthreads();
   for (int m = threadIdx.x; m < n_mt; m += kSegThreads) {
@@ -189,7 +202,7 @@ seg_fill_kernel(int64_t n, CamArgs cam, int n_mt, uint32_t gbits, const float* _
     const int64_t i = b0 + (int64_t)r * kSegThreads + threadIdx.x;
     if (i >= n || f_cnt[i] == 0) continue;
     const uint64_t c = ((uint64_t)(f_key[i] - dmin) << gbits) | (uint64_t)i;
-    visit_macro_tiles(fields(i), cam.width, cam.height, cam.n_mt_x, cam.n_mt_y, [&](uint32_t mt) {
+    visit(i, [&](uint32_t mt) {
       const uint32_t at = base[mt] + atomicAdd(&cnt[mt], 1u);
       if (at < max_pairs) comp[at] = c;
     });
@@ -352,13 +365,14 @@ static uint32_t id_bits(int64_t n) {
 
 hipError_t launch_seg_count(int64_t n, CamArgs cam, const float* f_mx, const float* f_my,
                             const float* f_a, const float* f_b, const float* f_c,
-                            const float* f_tau, const uint32_t* f_cnt, SegBuffers sb,
-                            uint32_t max_pairs, DeviceCounters* dc, hipStream_t s) {
+                            const float* f_tau, const uint32_t* f_cnt, const uint32_t* f_span,
+                            SegBuffers sb, uint32_t max_pairs, DeviceCounters* dc, hipStream_t s) {
   const int n_mt = cam.n_mt_x * cam.n_mt_y;
   const unsigned batches = (unsigned)((n + kSegBatch - 1) / kSegBatch);
   if (batches > 0)
     hipLaunchKernelGGL(seg_count_kernel, dim3(batches), dim3(kSegThreads), n_mt * sizeof(uint32_t),
-                       s, n, cam, n_mt, f_mx, f_my, f_a, f_b, f_c, f_tau, f_cnt, sb.seg_count, dc);
+                       s, n, cam, n_mt, f_mx, f_my, f_a, f_b, f_c, f_tau, f_cnt, f_span, sb.seg_count,
+                       dc);
   hipLaunchKernelGGL(seg_scan_kernel, dim3(1), dim3(kSegScanThreads), 0, s, n_mt, max_pairs,
                      sb.seg_count, sb.mt_off, sb.cursor, sb.chunk_off, sb.blk_off, dc);
   return hipGetLastError();
@@ -366,14 +380,15 @@ hipError_t launch_seg_count(int64_t n, CamArgs cam, const float* f_mx, const flo
 
 hipError_t launch_seg_fill(int64_t n, CamArgs cam, const float* f_mx, const float* f_my,
                            const float* f_a, const float* f_b, const float* f_c, const float* f_tau,
-                           const uint32_t* f_key, const uint32_t* f_cnt, SegBuffers sb,
-                           uint32_t max_pairs, DeviceCounters* dc, hipStream_t s) {
+                           const uint32_t* f_key, const uint32_t* f_cnt, const uint32_t* f_span,
+                           SegBuffers sb, uint32_t max_pairs, DeviceCounters* dc, hipStream_t s) {
   const int n_mt = cam.n_mt_x * cam.n_mt_y;
   const unsigned batches = (unsigned)((n + kSegBatch - 1) / kSegBatch);
   if (batches > 0)
     hipLaunchKernelGGL(seg_fill_kernel, dim3(batches), dim3(kSegThreads),
                        2 * n_mt * sizeof(uint32_t), s, n, cam, n_mt, id_bits(n), f_mx, f_my, f_a,
-                       f_b, f_c, f_tau, f_key, f_cnt, sb.cursor, dc, max_pairs, sb.comp);
+                       f_b, f_c, f_tau, f_key, f_cnt, f_span, sb.cursor, dc, max_pairs,
+                       sb.comp);
   return hipGetLastError();
 }
 
