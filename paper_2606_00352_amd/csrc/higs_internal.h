@@ -21,7 +21,9 @@ constexpr int kMaxBatch = 1024;  // largest B_r the rasteriser's LDS holds
 constexpr int kProjBlock = 256;  // gaussians per projection / emission block
 
 // Radix sort geometry.
-constexpr int kRadixBits = 8;
+// 9-bit digits: a 1080p frame's keys (10 macro-tile bits, ~25 depth bits) take
+// four passes instead of five 8-bit ones
+constexpr int kRadixBits = 9;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortThreads = 512;
 constexpr int kSortItems = 12;                         // keys per thread

@@ -5,11 +5,11 @@
 // (macro-tile << d | depth bits - min, d the bits of the frame's depth range)
 // with the gaussian id as value.  Pairs arrive in gaussian-id order and every
 // pass is stable, so the result is ordered by (macro-tile, depth, id).  One
-// pass per 8-bit digit of the d + ceil(log2 n_mt) significant key bits, each a
+// pass per 9-bit digit of the d + ceil(log2 n_mt) significant key bits, each a
 // single "onesweep" kernel:
 //   - a persistent grid claims 6144-key tiles from a device counter, so tile
 //     t's predecessors are always resident (forward progress of the look-back);
-//   - each wave ranks its 768 keys stably with 8 ballots per key (wave-level
+//   - each wave ranks its 768 keys stably with 9 ballots per key (wave-level
 //     multisplit) against a wave-private digit histogram in LDS;
 //   - per digit, the tile publishes its count and looks back over the
 //     preceding tiles' published counts/prefixes (decoupled look-back, one
@@ -77,7 +77,7 @@ sort_hist_kernel(const uint64_t* __restrict__ keys, const DeviceCounters* __rest
   }
 }
 
-// One block of 256 threads (one per digit): per pass, skip flag, source
+// One block of kRadix threads (one per digit): per pass, skip flag, source
 // buffer and the exclusive digit bases.
 __global__ void __launch_bounds__(kRadix)
 sort_plan_kernel(const uint32_t* __restrict__ hist, DeviceCounters* __restrict__ dc, int n_passes,
@@ -91,7 +91,7 @@ sort_plan_kernel(const uint32_t* __restrict__ hist, DeviceCounters* __restrict__
     const uint32_t c = hist[p * kRadix + d];
     // a pass above the key width, or one whose digit every key shares
     const int trivial = __syncthreads_or(c == n) || p >= np;
-    // exclusive scan of the 256 digit counts
+    // exclusive scan of the digit counts
     uint32_t v = c;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -194,7 +194,7 @@ onesweep_kernel(int pass, uint32_t epoch, uint64_t* __restrict__ k0, uint32_t* _
     }
     __syncthreads();
 
-    // per digit (threads 0..255, whole waves): wave prefixes, tile count,
+    // per digit (threads 0..kRadix-1, whole waves): wave prefixes, tile count,
     // publish, look back
     const int d = tid;
     uint32_t v = 0, tot = 0, prefix = 0;

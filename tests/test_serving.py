@@ -19,7 +19,9 @@ def test_context_footprint_counts_every_array():
     n_mt = ((W + 63) // 64) * ((H + 31) // 32)
     nblk = (G + 255) // 256
     tiles = (P + 6143) // 6144
-    want = (G * (9 * 4 + 48) + 2 * nblk * 4 + P * 24 + 8 * 256 * 4 + (8 + 8 * 256) * 4 + tiles * 256 * 8
+    radix = 512                           # 9-bit sort digits
+    want = (G * (9 * 4 + 48) + 2 * nblk * 4 + P * 24 + 8 * radix * 4 + (8 + 8 * radix) * 4
+            + tiles * radix * 8
             + 2 * (n_mt + 1) * 4 + B * 16 + B * 32 * 64 * 16)
     got = higs.ctx_footprint(G, P, B, W, H)
     assert 0 < got - want <= 512          # plus the frame counters
