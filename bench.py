@@ -313,7 +313,7 @@ def main():
     # sizes per view (outside the timed region), evaluation count by the
     # rasteriser's own counter
     ctx.set_debug(higs.DEBUG_COUNT_EVALS)
-    sizes = {"visible": [], "pairs": [], "batches": [], "passes": [], "evals": []}
+    sizes = {"visible": [], "pairs": [], "batches": [], "passes": [], "evals": [], "pair_bytes": []}
     for cam in cams:
         ctx.render(*tens, cam, image)
         c = ctx.counts()
@@ -322,6 +322,7 @@ def main():
         sizes["batches"].append(c.n_batches)
         sizes["passes"].append(c.sort_passes)
         sizes["evals"].append(c.n_evaluations)
+        sizes["pair_bytes"].append(c.sort_pair_bytes)
     ctx.set_debug(0)
     mean = {k: float(np.mean(v)) for k, v in sizes.items()}
     n = scene.n
@@ -329,16 +330,21 @@ def main():
     seg = args.sort == "segmented"
     # fill: reads the pair count of every gaussian (4 B); onesweep mode: the
     # macro-tile span word and depth key of every visible one (8 B), and writes
-    # a 12-B (key, id) pair per pair; segmented mode: the six binning fields
-    # and depth key of every visible one (28 B), and one 8-B composite per pair
-    fill_bytes = 4 * n + (28 if seg else 8) * mean["visible"] + (8 if seg else 12) * mean["pairs"]
+    # each pair (8 B when key and id share a word, else 12 B); segmented mode:
+    # the six binning fields and depth key of every visible one (28 B), and one
+    # 8-B composite per pair
+    pb = mean["pair_bytes"]
+    fill_bytes = 4 * n + (28 if seg else 8) * mean["visible"] + (8 if seg else pb) * mean["pairs"]
     rl["fill"] = ("hbm", fill_bytes / (timers["fill"] * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", fill_bytes)
     proj_bytes = PROJECT_B_PER_GAUSSIAN * n + PROJECT_B_PER_VISIBLE * mean["visible"]
     rl["project"] = ("hbm", proj_bytes / (timers["project"] * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", proj_bytes)
     # onesweep: the digit histogram reads every key (8 B), each moving pass
-    # reads and writes key and id (24 B); segmented: every composite read once
-    # (8 B) and its id written once (4 B), the floor of any segment sort
-    sort_bytes = mean["pairs"] * (12 if seg else 8 + 24 * mean["passes"])
+    # reads and writes each pair (2 x 8 B one-word, 2 x 12 B key and id), and
+    # with one-word pairs the last pass also writes the ids (4 B); segmented:
+    # every composite read once (8 B) and its id written once (4 B), the floor
+    # of any segment sort
+    sort_bytes = mean["pairs"] * (12 if seg else
+                                  8 + 2 * pb * mean["passes"] + (4 if pb == 8 else 0))
     rl["sort"] = ("hbm", sort_bytes / (timers["sort"] * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", sort_bytes)
     ops = mean["evals"] * RASTER_OPS_PER_EVAL
     rl["raster"] = ("alu", ops / (timers["raster"] * 1e-3) / 1e12, VALU_PEAK_TOPS, "Tops/s", ops)

@@ -115,6 +115,11 @@ typedef struct {
   int64_t n_evaluations; /* pixel-gaussian evaluations of the rasteriser
                             (64 per gaussian per render tile visited), or -1
                             unless HIGS_DEBUG_COUNT_EVALS is set */
+  int32_t sort_pair_bytes; /* bytes per pair that each radix pass reads and
+                              writes: 8 when key and gaussian id share one
+                              64-bit word, 12 when the id travels in an array
+                              of its own; 0 in segmented mode */
+  int32_t reserved;
 } higs_counts;
 
 /* Writes the paper's defaults into *p. */

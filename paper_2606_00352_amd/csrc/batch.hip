@@ -21,7 +21,8 @@ mt_offsets_kernel(int n_mt, const uint64_t* __restrict__ k0, const uint64_t* __r
   if (m > n_mt) return;
   const int lane = threadIdx.x & 63;
   const uint64_t* __restrict__ keys = dc->sort_final ? k1 : k0;
-  const uint64_t target = (uint64_t)m << depth_bits(dc->key_min, dc->key_max);
+  // keys are macro-tile << d | depth, shifted above the id in one-word pairs
+  const uint64_t target = (uint64_t)m << (depth_bits(dc->key_min, dc->key_max) + dc->id_shift);
   uint32_t lo = 0, hi = dc->n_pairs;  // answer in [lo, hi]
   while (hi - lo > 64) {
     const uint32_t step = (hi - lo + 63) / 64;

@@ -58,8 +58,8 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 16;  // blocks per thread per chunk
 __global__ void __launch_bounds__(kScanThreads)
-scan_kernel(uint32_t n_blocks, uint32_t* __restrict__ sums, uint32_t max_pairs,
-            DeviceCounters* __restrict__ dc) {
+scan_kernel(uint32_t n_blocks, uint32_t* __restrict__ sums, uint32_t max_pairs, int mt_bits,
+            int id_bits, DeviceCounters* __restrict__ dc) {
   __shared__ uint32_t wave_tot[2][kScanThreads / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t carry_p = 0, carry_v = 0;  // same in every thread
@@ -132,15 +132,23 @@ scan_kernel(uint32_t n_blocks, uint32_t* __restrict__ sums, uint32_t max_pairs,
     dc->n_pairs = total < max_pairs ? total : max_pairs;
     dc->n_visible = carry_v;
     if (total > max_pairs) dc->overflow |= HIGS_OVF_PAIRS;
+    // when the key (macro-tile and depth bits, plus one bit of headroom for
+    // the segment search's end target) and the gaussian id fit one 64-bit
+    // word, a pair is that word alone: the sort moves 8 bytes per pair
+    // instead of 12, and ties still break by id
+    const int kbits = mt_bits + (int)depth_bits(dc->key_min, dc->key_max) + 1;
+    dc->id_shift = (id_bits > 0 && kbits + id_bits <= 64) ? (uint32_t)id_bits : 0u;
   }
 }
 
 hipError_t launch_scan(int64_t n, const uint32_t* cnt, uint32_t* block_sums, uint32_t max_pairs,
-                       DeviceCounters* dc, hipStream_t s) {
+                       int mt_bits, DeviceCounters* dc, hipStream_t s) {
   (void)cnt;
   const uint32_t n_blocks = (uint32_t)((n + kProjBlock - 1) / kProjBlock);
+  int id_bits = 0;  // bits of the largest gaussian id
+  for (int64_t v = n > 1 ? n - 1 : 0; v; v >>= 1) ++id_bits;
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, s, n_blocks, block_sums,
-                     max_pairs, dc);
+                     max_pairs, mt_bits, id_bits, dc);
   return hipGetLastError();
 }
 
@@ -180,6 +188,7 @@ fill_kernel(int64_t n, CamArgs cam, const float* __restrict__ f_mx, const float*
   __syncthreads();
   const uint32_t dmin = dc->key_min;
   const uint32_t dbits = depth_bits(dmin, dc->key_max);
+  const uint32_t ish = dc->id_shift;
 #pragma unroll
   for (int k = 0; k < kFillBlocks; ++k) {
     if (__ballot(cnt[k] > 0) == 0) continue;  // whole wave invisible in this block
@@ -191,8 +200,13 @@ fill_kernel(int64_t n, CamArgs cam, const float* __restrict__ f_mx, const float*
     const uint32_t gid = (uint32_t)i;
     auto emit = [&](uint32_t mt) {
       if (at < max_pairs) {
-        keys[at] = ((uint64_t)mt << dbits) | depth;
-        vals[at] = gid;
+        const uint64_t key = ((uint64_t)mt << dbits) | depth;
+        if (ish) {
+          keys[at] = (key << ish) | gid;
+        } else {
+          keys[at] = key;
+          vals[at] = gid;
+        }
       }
       ++at;
     };

@@ -458,7 +458,7 @@ int higs_bin_sort(higs_ctx* c, void* stream) {
   {
     TimerScope ts(c, HIGS_TIMER_SCAN, s);
     rc = hip_err(launch_scan(c->n > 0 ? c->n : 0, c->f_cnt, c->block_sums,
-                             (uint32_t)c->max_pairs, c->dc, s));
+                             (uint32_t)c->max_pairs, n_bits((uint32_t)(c->n_mt - 1)), c->dc, s));
   }
   if (rc) return rc;
   {
@@ -592,6 +592,8 @@ int higs_get_counts(higs_ctx* c, higs_counts* out) {
   out->n_evaluations = (c->stage >= 4 && (c->debug_flags & HIGS_DEBUG_COUNT_EVALS))
                            ? (int64_t)h.n_evals * 64
                            : -1;
+  out->sort_pair_bytes = (c->stage < 2 || c->segmented()) ? 0 : (h.id_shift ? 8 : 12);
+  out->reserved = 0;
   return HIGS_OK;
 }
 
@@ -676,20 +678,30 @@ int higs_debug_copy(higs_ctx* c, int which, void* host_dst, size_t bytes) {
         k = c->keys[h.sort_final & 1u];
         v = c->vals[h.sort_final & 1u];
       }
-      const size_t kb = bytes < np * 8 ? bytes : np * 8;
-      if (hipMemcpy(dst, k, kb, hipMemcpyDeviceToHost) != hipSuccess) return HIGS_E_HIP;
+      std::vector<uint64_t> words(np);
+      if (np && hipMemcpy(words.data(), k, np * 8, hipMemcpyDeviceToHost) != hipSuccess)
+        return HIGS_E_HIP;
+      std::vector<uint32_t> ids(np);
+      const uint32_t ish = h.id_shift;
+      if (ish) {  // one-word pairs: key << ish | id
+        for (size_t q = 0; q < np; ++q) {
+          ids[q] = (uint32_t)(words[q] & ((1ull << ish) - 1ull));
+          words[q] >>= ish;
+        }
+      } else if (np && hipMemcpy(ids.data(), v, np * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+        return HIGS_E_HIP;
+      }
       // keys are stored range-compressed; hand them back as
       // macro-tile << 32 | float32 depth bits
       const uint32_t dbits = depth_bits(h.key_min, h.key_max);
-      uint64_t* hk = reinterpret_cast<uint64_t*>(dst);
-      for (size_t q = 0; q < kb / 8; ++q) {
-        const uint64_t mt = dbits >= 64 ? 0 : hk[q] >> dbits;
-        const uint64_t dep = hk[q] & ((dbits >= 64 ? 0ull : (1ull << dbits)) - 1ull);
-        hk[q] = (mt << 32) | (uint64_t)(uint32_t)(dep + h.key_min);
+      for (size_t q = 0; q < np; ++q) {
+        const uint64_t mt = dbits >= 64 ? 0 : words[q] >> dbits;
+        const uint64_t dep = words[q] & ((dbits >= 64 ? 0ull : (1ull << dbits)) - 1ull);
+        words[q] = (mt << 32) | (uint64_t)(uint32_t)(dep + h.key_min);
       }
-      if (bytes > np * 8 &&
-          hipMemcpy(dst + np * 8, v, bytes - np * 8, hipMemcpyDeviceToHost) != hipSuccess)
-        return HIGS_E_HIP;
+      const size_t kb = bytes < np * 8 ? bytes : np * 8;
+      memcpy(dst, words.data(), kb);
+      if (bytes > np * 8) memcpy(dst + np * 8, ids.data(), bytes - np * 8);
       return HIGS_OK;
     }
     case HIGS_DBG_MT_OFFSETS:

@@ -67,7 +67,9 @@ struct DeviceCounters {
   uint32_t bwd_next;        // work counter of the persistent raster adjoint
   uint32_t seg_max;         // largest segment (segmented sort)
   uint32_t seg_next[1 + 20];  // work counters: chunk sort, then one per merge level
-  uint32_t pad[8];
+  uint32_t id_shift;        // > 0: each pair is one word key << id_shift | id (see scan_kernel)
+  uint32_t sort_last;       // last radix pass that moves data (it writes the id array)
+  uint32_t pad[6];
 };
 
 // Look-back status words (sort passes): 30-bit epoch,
@@ -113,7 +115,7 @@ hipError_t launch_project(int64_t n, const float* means, const float* scales, co
                           hipStream_t s);
 
 hipError_t launch_scan(int64_t n, const uint32_t* cnt, uint32_t* block_sums, uint32_t max_pairs,
-                       DeviceCounters* dc, hipStream_t s);
+                       int mt_bits, DeviceCounters* dc, hipStream_t s);
 
 hipError_t launch_fill(int64_t n, CamArgs cam, const float* f_mx, const float* f_my,
                        const float* f_a, const float* f_b, const float* f_c, const float* f_tau,

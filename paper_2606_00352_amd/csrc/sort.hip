@@ -4,7 +4,9 @@
 // A stable least-significant-digit radix sort over the composite 64-bit key
 // (macro-tile << d | depth bits - min, d the bits of the frame's depth range)
 // with the gaussian id as value.  Pairs arrive in gaussian-id order and every
-// pass is stable, so the result is ordered by (macro-tile, depth, id).  One
+// pass is stable, so the result is ordered by (macro-tile, depth, id).  When
+// key and id fit one word (key << g | id, g the id bits) the passes move that
+// word alone and the last moving pass also writes the id array.  One
 // pass per 9-bit digit of the d + ceil(log2 n_mt) significant key bits, each a
 // single "onesweep" kernel:
 //   - a persistent grid claims 6144-key tiles from a device counter, so tile
@@ -45,6 +47,7 @@ sort_hist_kernel(const uint64_t* __restrict__ keys, const DeviceCounters* __rest
   // over copies keeps the LDS atomics of one wave from piling on one address
   __shared__ uint32_t h[kHistCopies][kMaxPasses * kRadix];
   const uint32_t n = dc->n_pairs;
+  const uint32_t ish = dc->id_shift;  // key bits start above the id in a one-word pair
   // digit positions above the frame's key width are zero in every key
   const int np = min(n_passes, (mt_bits + (int)depth_bits(dc->key_min, dc->key_max) +
                                 kRadixBits - 1) / kRadixBits);
@@ -65,7 +68,8 @@ sort_hist_kernel(const uint64_t* __restrict__ keys, const DeviceCounters* __rest
     for (int b = 0; b < kHistBatch; ++b) {
       if (i0 + (uint32_t)b * stride >= n) break;
       for (int p = 0; p < np; ++p)
-        atomicAdd(&mine[p * kRadix + (uint32_t)((key[b] >> (kRadixBits * p)) & (kRadix - 1))], 1u);
+        atomicAdd(&mine[p * kRadix + (uint32_t)((key[b] >> (ish + kRadixBits * p)) & (kRadix - 1))],
+                  1u);
     }
   }
   __syncthreads();
@@ -78,7 +82,8 @@ sort_hist_kernel(const uint64_t* __restrict__ keys, const DeviceCounters* __rest
 }
 
 // One block of kRadix threads (one per digit): per pass, skip flag, source
-// buffer and the exclusive digit bases.
+// buffer and the exclusive digit bases.  One-word pairs need one moving pass
+// to write the id array: if no digit varies, pass 0 moves anyway.
 __global__ void __launch_bounds__(kRadix)
 sort_plan_kernel(const uint32_t* __restrict__ hist, DeviceCounters* __restrict__ dc, int n_passes,
                  int mt_bits, uint32_t* __restrict__ plan, uint32_t* __restrict__ base) {
@@ -86,11 +91,16 @@ sort_plan_kernel(const uint32_t* __restrict__ hist, DeviceCounters* __restrict__
   const uint32_t n = dc->n_pairs;
   const int np = (mt_bits + (int)depth_bits(dc->key_min, dc->key_max) + kRadixBits - 1) / kRadixBits;
   const int d = threadIdx.x, lane = d & 63, wave = d >> 6;
+  // a pass above the key width, or one whose digit every key shares, is skipped
+  uint32_t skip = 0;
+  for (int p = 0; p < n_passes; ++p)
+    if (__syncthreads_or(hist[p * kRadix + d] == n) || p >= np) skip |= 1u << p;
+  const uint32_t all = (1u << n_passes) - 1u;
+  if (dc->id_shift && skip == all) skip &= ~1u;
   uint32_t cur = 0, moved = 0;
   for (int p = 0; p < n_passes; ++p) {
     const uint32_t c = hist[p * kRadix + d];
-    // a pass above the key width, or one whose digit every key shares
-    const int trivial = __syncthreads_or(c == n) || p >= np;
+    const int trivial = (skip >> p) & 1u;
     // exclusive scan of the digit counts
     uint32_t v = c;
 #pragma unroll
@@ -113,6 +123,7 @@ sort_plan_kernel(const uint32_t* __restrict__ hist, DeviceCounters* __restrict__
   if (d == 0) {
     dc->sort_final = cur;
     dc->sort_passes = moved;
+    dc->sort_last = skip == all ? 0xffffffffu : 31u - (uint32_t)__clz(all & ~skip);
   }
 }
 
@@ -147,7 +158,13 @@ onesweep_kernel(int pass, uint32_t epoch, uint64_t* __restrict__ k0, uint32_t* _
   const uint32_t* __restrict__ vin = src ? v1 : v0;
   uint64_t* __restrict__ kout = src ? k0 : k1;
   uint32_t* __restrict__ vout = src ? v0 : v1;
-  const uint32_t shift = (uint32_t)(kRadixBits * pass);
+  // one-word pairs: the digit sits above the id, no value array moves, and
+  // the last moving pass writes the ids out of the words
+  const uint32_t ish = dc->id_shift;
+  const bool one_word = ish != 0;
+  const bool write_ids = one_word && dc->sort_last == (uint32_t)pass;
+  const uint64_t id_mask = (1ull << ish) - 1ull;
+  const uint32_t shift = ish + (uint32_t)(kRadixBits * pass);
   const uint32_t n = dc->n_pairs;
   const uint32_t n_tiles = (n + kSortTile - 1) / kSortTile;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -170,7 +187,7 @@ onesweep_kernel(int pass, uint32_t epoch, uint64_t* __restrict__ k0, uint32_t* _
       const uint32_t idx = wbase + k * 64 + lane;
       if (idx < n) {
         key[k] = kin[idx];
-        val[k] = vin[idx];
+        val[k] = one_word ? 0u : vin[idx];
       } else {
         key[k] = ~0ull;  // sorts last, never written out
         val[k] = 0;
@@ -263,8 +280,15 @@ onesweep_kernel(int pass, uint32_t epoch, uint64_t* __restrict__ k0, uint32_t* _
         const uint64_t kk = L.buf.keys[j];
         const uint32_t d = (uint32_t)(kk >> shift) & (kRadix - 1);
         dst[k] = L.gbase[d] + j;
-        if (dst[k] < n) kout[dst[k]] = kk;
+        if (dst[k] < n) {
+          kout[dst[k]] = kk;
+          if (write_ids) vout[dst[k]] = (uint32_t)(kk & id_mask);
+        }
       }
+    }
+    if (one_word) {  // nothing else moves
+      __syncthreads();
+      continue;
     }
     __syncthreads();
 #pragma unroll

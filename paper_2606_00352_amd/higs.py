@@ -56,7 +56,8 @@ class Counts(ctypes.Structure):
     _fields_ = [("n_gaussians", ctypes.c_int64), ("n_visible", ctypes.c_int64),
                 ("n_pairs", ctypes.c_int64), ("n_batches", ctypes.c_int64),
                 ("overflow", ctypes.c_uint32), ("sort_passes", ctypes.c_int32),
-                ("n_evaluations", ctypes.c_int64)]
+                ("n_evaluations", ctypes.c_int64), ("sort_pair_bytes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 MAX_CLASSES = 4
