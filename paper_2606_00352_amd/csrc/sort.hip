@@ -130,6 +130,7 @@ sort_plan_kernel(const uint32_t* __restrict__ hist, DeviceCounters* __restrict__
 constexpr int kWaves = kSortThreads / 64;
 static_assert(kSortThreads >= kRadix && kSortThreads % 64 == 0, "one thread per digit, whole waves");
 constexpr int kWaveItems = 64 * kSortItems;  // 768 keys per wave
+constexpr int kLookWindow = 4;               // look-back words loaded per round trip
 
 struct SortLds {
   // the tile regrouped by digit: keys first, then (reusing the space) values
@@ -234,21 +235,34 @@ onesweep_kernel(int pass, uint32_t epoch, uint64_t* __restrict__ k0, uint32_t* _
       }
       if (lane == 63) L.wave_tot[wave] = v;
       if (tile > 0) {
+        // kLookWindow predecessors per round trip: their words are loaded
+        // together, then taken nearest first until an inclusive prefix or one
+        // not yet published (the next round starts there)
         int64_t t = (int64_t)tile - 1;
         uint32_t spins = 0;
+        bool done = false;
         while (t >= 0) {
-          const uint64_t w = ld_status(status + (size_t)t * kRadix + d);
-          const uint32_t flag = (uint32_t)(w >> 32) & 3u;
-          if ((uint32_t)(w >> 34) != epoch || flag == 0) {  // not published yet
-            if (++spins > kMaxSpins) {  // cannot happen unless a tile was lost
-              atomicOr(&dc->overflow, kErrSortStall);
-              break;
-            }
-            continue;
+          uint64_t w[kLookWindow];
+#pragma unroll
+          for (int k = 0; k < kLookWindow; ++k)
+            w[k] = t - k >= 0 ? ld_status(status + (size_t)(t - k) * kRadix + d) : 0ull;
+          int used = 0;
+#pragma unroll
+          for (int k = 0; k < kLookWindow; ++k) {
+            if (used != k || t - k < 0) break;
+            const uint32_t flag = (uint32_t)(w[k] >> 32) & 3u;
+            if ((uint32_t)(w[k] >> 34) != epoch || flag == 0) break;  // not published yet
+            prefix += (uint32_t)w[k];
+            used = k + 1;
+            if (flag == kFlagPrefix) done = true;
+            if (done) break;
           }
-          prefix += (uint32_t)w;
-          if (flag == kFlagPrefix) break;
-          --t;
+          if (done) break;
+          if (used == 0 && ++spins > kMaxSpins) {  // cannot happen unless a tile was lost
+            atomicOr(&dc->overflow, kErrSortStall);
+            break;
+          }
+          t -= used;
         }
         st_status(st, status_word(epoch, kFlagPrefix, prefix + tot));
       }
