@@ -24,12 +24,12 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # lane-instructions/s: 256 CUs x 
 # Algorithmic bytes per unit (what each kernel must move):
 #   project: reads means+scales+quats+opacity 44 B per gaussian and 192 B of SH
 #            per visible gaussian; writes depth key + count 8 B per gaussian and
-#            binning fields 24 B + span word 4 B + raster record 48 B per visible
-#            gaussian.
-#   sort:    histogram read 8 B per pair, then per executed pass 12 B read +
-#            12 B written per pair.
+#            span word 4 B + raster record 48 B per visible gaussian (the 24 B
+#            of binning fields only for the few whose macro-tile list does not
+#            fit the span word: not counted).
+#   sort:    see the sort roofline below.
 PROJECT_B_PER_GAUSSIAN = 44 + 8
-PROJECT_B_PER_VISIBLE = 192 + 24 + 4 + 48
+PROJECT_B_PER_VISIBLE = 192 + 4 + 48
 # Arithmetic operations per pixel-gaussian evaluation of the raster inner loop
 # (dx, dy, two for u, v, two for q, exp2, opacity product, clamp, threshold
 # test, weight, three colour FMAs, transmittance update).
@@ -328,13 +328,12 @@ def main():
     n = scene.n
     rl = {}
     seg = args.sort == "segmented"
-    # fill: reads the pair count of every gaussian (4 B); onesweep mode: the
-    # macro-tile span word and depth key of every visible one (8 B), and writes
-    # each pair (8 B when key and id share a word, else 12 B); segmented mode:
-    # the six binning fields and depth key of every visible one (28 B), and one
-    # 8-B composite per pair
+    # fill: reads the pair count of every gaussian (4 B) and the macro-tile span
+    # word and depth key of every visible one (8 B); writes each pair (onesweep
+    # mode: 8 B when key and id share a word, else 12 B; segmented mode: one 8-B
+    # composite)
     pb = mean["pair_bytes"]
-    fill_bytes = 4 * n + (28 if seg else 8) * mean["visible"] + (8 if seg else pb) * mean["pairs"]
+    fill_bytes = 4 * n + 8 * mean["visible"] + (8 if seg else pb) * mean["pairs"]
     rl["fill"] = ("hbm", fill_bytes / (timers["fill"] * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", fill_bytes)
     proj_bytes = PROJECT_B_PER_GAUSSIAN * n + PROJECT_B_PER_VISIBLE * mean["visible"]
     rl["project"] = ("hbm", proj_bytes / (timers["project"] * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s", proj_bytes)

@@ -270,7 +270,10 @@ int higs_get_counts(higs_ctx* ctx, higs_counts* out);
 
 /* Intermediate buffers that higs_debug_copy can read back (tests). */
 #define HIGS_DBG_PROJ 1     /* float32 [8][n]: mx, my, a, b, c, tau, key bits, count bits
-                               (rows of culled gaussians: key = 0, count = 0, rest undefined) */
+                               (rows of culled gaussians: key = 0, count = 0, rest undefined;
+                               mx .. tau are stored for every gaussian that passes the
+                               culling only under HIGS_DEBUG_PROJ_FIELDS, otherwise only
+                               for those whose macro-tile list the emission re-derives) */
 #define HIGS_DBG_RECORDS 2  /* float32 [n][12]: mx, my, l0, l1, l2, o, r, g, b, tau, 0, 0
                                (defined for gaussians with count > 0) */
 #define HIGS_DBG_PAIRS 3    /* uint64 keys [n_pairs] then uint32 ids [n_pairs], emission order
@@ -290,6 +293,11 @@ int higs_get_counts(higs_ctx* ctx, higs_counts* out);
 /* HIGS_DEBUG_COUNT_EVALS makes the rasteriser count its evaluations
  * (reported in higs_counts.n_evaluations; adds one atomic per tile). */
 #define HIGS_DEBUG_COUNT_EVALS 2
+/* HIGS_DEBUG_PROJ_FIELDS makes the projection store the six binning fields of
+ * every gaussian that passes the culling (24 bytes each), for HIGS_DBG_PROJ.
+ * Without it they are stored only where the emission needs them: gaussians
+ * whose macro-tile list does not fit the compact span word. */
+#define HIGS_DEBUG_PROJ_FIELDS 4
 int higs_set_debug(higs_ctx* ctx, int flags);
 
 /* Copies `bytes` bytes of buffer `which` (HIGS_DBG_*) into HOST memory

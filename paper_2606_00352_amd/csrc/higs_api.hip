@@ -390,7 +390,8 @@ int higs_project(higs_ctx* c, int64_t n, const float* means, const float* scales
     TimerScope ts(c, HIGS_TIMER_PROJECT, s);
     rc = hip_err(launch_project(n, means, scales, quats, opacities, sh, c->ca, c->pa, c->f_mx,
                                 c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau, c->f_key, c->f_cnt,
-                                c->f_span, c->rec, c->block_sums, c->dc, s));
+                                c->f_span, c->rec, c->block_sums, c->dc,
+                                (c->debug_flags & HIGS_DEBUG_PROJ_FIELDS) != 0, s));
   }
   if (rc) return rc;
   c->stage = 1;

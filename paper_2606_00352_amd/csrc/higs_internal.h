@@ -112,7 +112,7 @@ hipError_t launch_project(int64_t n, const float* means, const float* scales, co
                           float* f_mx, float* f_my, float* f_a, float* f_b, float* f_c,
                           float* f_tau, uint32_t* f_key, uint32_t* f_cnt, uint32_t* f_span,
                           RasterRecord* rec, uint32_t* block_sums, DeviceCounters* dc,
-                          hipStream_t s);
+                          bool all_fields, hipStream_t s);
 
 hipError_t launch_scan(int64_t n, const uint32_t* cnt, uint32_t* block_sums, uint32_t max_pairs,
                        int mt_bits, DeviceCounters* dc, hipStream_t s);

@@ -179,7 +179,8 @@ project_kernel(int64_t n, const float* __restrict__ means, const float* __restri
                float* __restrict__ f_b, float* __restrict__ f_c, float* __restrict__ f_tau,
                uint32_t* __restrict__ f_key, uint32_t* __restrict__ f_cnt,
                uint32_t* __restrict__ f_span, RasterRecord* __restrict__ rec,
-               uint32_t* __restrict__ block_sums, DeviceCounters* __restrict__ dc, bool sh_vec4) {
+               uint32_t* __restrict__ block_sums, DeviceCounters* __restrict__ dc, bool sh_vec4,
+               bool all_fields) {
   __shared__ uint32_t wave_min[kProjBlock / 64], wave_max[kProjBlock / 64];
   __shared__ uint32_t wave_sums[2][kProjBlock / 64];
   const int64_t i = (int64_t)blockIdx.x * kProjBlock + threadIdx.x;
@@ -215,13 +216,18 @@ project_kernel(int64_t n, const float* __restrict__ means, const float* __restri
       SpanTracker span;
       cnt = visit_macro_tiles_ji(f, cam.width, cam.height, cam.n_mt_x, cam.n_mt_y,
                                  [&](int j, int ic) { span.add(j, ic); });
-      if (cnt > 0) f_span[i] = span.encode();
-      f_mx[i] = f.mx;
-      f_my[i] = f.my;
-      f_a[i] = f.a;
-      f_b[i] = f.b;
-      f_c[i] = f.c;
-      f_tau[i] = f.tau;
+      const uint32_t sw = cnt > 0 ? span.encode() : 0u;
+      if (cnt > 0) f_span[i] = sw;
+      // the binning fields: read again only for a list the span word cannot
+      // hold (and by the debug read-back)
+      if (all_fields || (cnt > 0 && sw == 0)) {
+        f_mx[i] = f.mx;
+        f_my[i] = f.my;
+        f_a[i] = f.a;
+        f_b[i] = f.b;
+        f_c[i] = f.c;
+        f_tau[i] = f.tau;
+      }
       if (cnt > 0) {
         kmin = key;
         kmax = key;
@@ -316,7 +322,7 @@ hipError_t launch_project(int64_t n, const float* means, const float* scales, co
                           float* f_mx, float* f_my, float* f_a, float* f_b, float* f_c,
                           float* f_tau, uint32_t* f_key, uint32_t* f_cnt, uint32_t* f_span,
                           RasterRecord* rec, uint32_t* block_sums, DeviceCounters* dc,
-                          hipStream_t s) {
+                          bool all_fields, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   // camera centre, -R^T t, for the SH view direction
   float3 campos;
@@ -327,7 +333,7 @@ hipError_t launch_project(int64_t n, const float* means, const float* scales, co
   hipLaunchKernelGGL(project_kernel, dim3(blocks), dim3(kProjBlock), 0, s, n, means, scales,
                      quats, opac, sh, cam, prm, campos, f_mx, f_my,
                      f_a, f_b, f_c, f_tau, f_key, f_cnt, f_span, rec, block_sums, dc,
-                     (reinterpret_cast<uintptr_t>(sh) & 15u) == 0);
+                     (reinterpret_cast<uintptr_t>(sh) & 15u) == 0, all_fields);
   return hipGetLastError();
 }
 

@@ -23,7 +23,8 @@ def gpu_frame(scene, cam, keep_pairs=True, ctx=None, **params):
         n = max(scene.n, 1)
         ctx = higs.Context(n, cam.width, cam.height, max_pairs=max(64 * n, 1 << 16), **params)
     if keep_pairs:
-        ctx.set_debug(higs.DEBUG_KEEP_PAIRS)
+        # every binning field stored too, for the projection's bit-exact check
+        ctx.set_debug(higs.DEBUG_KEEP_PAIRS | higs.DEBUG_PROJ_FIELDS)
     t = higs.scene_tensors(scene)
     img, T = higs.render(ctx, t, cam)
     torch.cuda.synchronize()

@@ -47,6 +47,12 @@ def _full(orc, scene, cam, n_random, n_untiled):
         c = ctx.counts()
         assert c.overflow == 0
         img, T = img.cpu().numpy(), T.cpu().numpy()
+        # the same frame with every binning field stored, for the projection's
+        # bit-exact check (the configuration above is the benchmark's)
+        ctx.set_debug(higs.DEBUG_PROJ_FIELDS)
+        img2, T2 = higs.render(ctx, t, cam)
+        torch.cuda.synchronize()
+        assert np.array_equal(img2.cpu().numpy(), img) and np.array_equal(T2.cpu().numpy(), T)
         report = {}
         gc.check_projection(orc, ctx, fr, report)
         gc.check_pairs_sort_batches(orc, ctx, fr, 1024, check_emission=False)

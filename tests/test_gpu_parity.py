@@ -116,9 +116,7 @@ def test_culled_inputs(orc):
     assert np.all(cnt[:6] == 0)
 
 
-def test_edge_straddling_and_huge_splat(orc):
-    """Splats straddling the image border, and one splat covering every
-    macro-tile (hundreds of pairs from one gaussian)."""
+def _border_and_huge_splat_scene():
     rng = np.random.default_rng(8)
     sc = scenes.uniform_scene(3000, seed=8)
     W, H = 256, 192
@@ -135,9 +133,38 @@ def test_edge_straddling_and_huge_splat(orc):
     sc.means[k] = [0.0, 0.0, 8.0]
     sc.scales[k] = [6.0, 4.0, 5.0]
     sc.opacities[k] = 0.95
+    return sc, cam, k
+
+
+def test_edge_straddling_and_huge_splat(orc):
+    """Splats straddling the image border, and one splat covering every
+    macro-tile (hundreds of pairs from one gaussian)."""
+    sc, cam, k = _border_and_huge_splat_scene()
     ctx, _ = _full_check(orc, sc, cam)
     cnt = ctx.proj_fields()["count"]
     assert cnt[k] == ctx.n_mt
+
+
+@SORT_MODES
+def test_binning_fields_stored_only_where_needed(orc, sort_mode):
+    """Without HIGS_DEBUG_PROJ_FIELDS the projection stores the binning fields
+    only for gaussians whose macro-tile list the emission derives again (the
+    splat over every macro-tile): sorted pairs, batches and image are the
+    same as with every field stored."""
+    from paper_2606_00352_amd import higs
+    sc, cam, k = _border_and_huge_splat_scene()
+    out = []
+    for flags in (higs.DEBUG_PROJ_FIELDS, 0):
+        ctx = higs.Context(sc.n, cam.width, cam.height, max_pairs=64 * sc.n, sort_mode=sort_mode)
+        ctx.set_debug(flags)
+        ctx, img, T = gc.gpu_frame(sc, cam, keep_pairs=False, ctx=ctx)
+        out.append((ctx.sorted_pairs(), ctx.batches(), img, T))
+        assert ctx.counts().n_pairs > ctx.n_mt
+    for a, b in zip(out[0], out[1]):
+        a = a if isinstance(a, tuple) else (a,)
+        b = b if isinstance(b, tuple) else (b,)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
 
 
 @SORT_MODES
