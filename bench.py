@@ -49,14 +49,14 @@ COPY_CALIBRATION_BYTES = 1 << 30
 MEASURED_TRAFFIC = {
     # profiles/frame_1080p_5p8m_hbm_traffic.md (sort: histogram + plan + every
     # onesweep dispatch of a frame)
-    "raster": {"src_sha256": "52f8d825e4cbdff496301c5115d017a477d11e72d83d5f30d7a13b05f7d7ba92",
-              "bytes_per_launch": 1514091113},
-    "project": {"src_sha256": "6d885e23504217b902497b8cebe99e1eebf4b706e7baf4cc0c0b74a42434ce63",
-               "bytes_per_launch": 1853978704},
-    "fill": {"src_sha256": "98ed87a5d120a8f0774c82de844185f31b63a83bc2416c056f459b5aa0788209",
-            "bytes_per_launch": 166149043},
-    "sort": {"src_sha256": "bd15a88f02773ae0b9f0ae82ff124eced46ce979cd15bbf2ba1b0c1d21c5c0cb",
-            "bytes_per_launch": 1174016785},
+    "raster": {"src_sha256": "15f0245e013c3b476b452da1179ecd7eaae9fad2222b09ce80fdebb5e19e27a2",
+              "bytes_per_launch": 1514697878},
+    "project": {"src_sha256": "93521bdb8a0cdc8d18daed2ead9532dc26707e5ed1c963225e3deb49b317caa7",
+               "bytes_per_launch": 1714750453},
+    "fill": {"src_sha256": "33c4b705ab57217834b07084250592c066c95fcee26b5d8d8643852fff34164f",
+            "bytes_per_launch": 134195976},
+    "sort": {"src_sha256": "b7669a1376975364d0af9f7bdcca5d5875f9bf3dadc251cc32ad82f959118d5b",
+            "bytes_per_launch": 923321318},
 }
 # the sources each figure depends on (the shared header holds the kernels' shapes)
 KERNEL_SOURCES = {"project": ("project.hip", "predicate.h", "higs_internal.h"),
