@@ -49,14 +49,14 @@ COPY_CALIBRATION_BYTES = 1 << 30
 MEASURED_TRAFFIC = {
     # profiles/frame_1080p_5p8m_hbm_traffic.md (sort: histogram + plan + every
     # onesweep dispatch of a frame)
-    "raster": {"src_sha256": "15f0245e013c3b476b452da1179ecd7eaae9fad2222b09ce80fdebb5e19e27a2",
-              "bytes_per_launch": 1514697878},
-    "project": {"src_sha256": "93521bdb8a0cdc8d18daed2ead9532dc26707e5ed1c963225e3deb49b317caa7",
-               "bytes_per_launch": 1714750453},
-    "fill": {"src_sha256": "33c4b705ab57217834b07084250592c066c95fcee26b5d8d8643852fff34164f",
-            "bytes_per_launch": 134195976},
-    "sort": {"src_sha256": "b7669a1376975364d0af9f7bdcca5d5875f9bf3dadc251cc32ad82f959118d5b",
-            "bytes_per_launch": 923321318},
+    "raster": {"src_sha256": "1da4501b167385202fb801afd66cbe32af9016bc647e573c011a9c0c5aa39a46",
+              "bytes_per_launch": 1514592617},
+    "project": {"src_sha256": "ad7413dd2a7a1a520c87f852f1bdfbe8ca46679de393ea252e841c33580e4268",
+               "bytes_per_launch": 1714746962},
+    "fill": {"src_sha256": "7512a00e46e7218273defd854560039b2ab3d60330bb6cfc331a8560d7e0a719",
+            "bytes_per_launch": 134195479},
+    "sort": {"src_sha256": "12d8ca4f321840e5acceeec27b95f47ada7a83cd1313b625ebf8e5b924dd47ff",
+            "bytes_per_launch": 917983361},
 }
 # the sources each figure depends on (the shared header holds the kernels' shapes)
 KERNEL_SOURCES = {"project": ("project.hip", "predicate.h", "higs_internal.h"),

@@ -298,6 +298,10 @@ int higs_get_counts(higs_ctx* ctx, higs_counts* out);
  * Without it they are stored only where the emission needs them: gaussians
  * whose macro-tile list does not fit the compact span word. */
 #define HIGS_DEBUG_PROJ_FIELDS 4
+/* HIGS_DEBUG_TWO_WORD_PAIRS keeps each pair's key and gaussian id in separate
+ * arrays even when they fit one 64-bit word (the layout frames with a wide key
+ * and many gaussians use), so that tests can run that sort path on any scene. */
+#define HIGS_DEBUG_TWO_WORD_PAIRS 8
 int higs_set_debug(higs_ctx* ctx, int flags);
 
 /* Copies `bytes` bytes of buffer `which` (HIGS_DBG_*) into HOST memory

@@ -142,11 +142,12 @@ scan_kernel(uint32_t n_blocks, uint32_t* __restrict__ sums, uint32_t max_pairs, 
 }
 
 hipError_t launch_scan(int64_t n, const uint32_t* cnt, uint32_t* block_sums, uint32_t max_pairs,
-                       int mt_bits, DeviceCounters* dc, hipStream_t s) {
+                       int mt_bits, bool allow_one_word, DeviceCounters* dc, hipStream_t s) {
   (void)cnt;
   const uint32_t n_blocks = (uint32_t)((n + kProjBlock - 1) / kProjBlock);
-  int id_bits = 0;  // bits of the largest gaussian id
-  for (int64_t v = n > 1 ? n - 1 : 0; v; v >>= 1) ++id_bits;
+  int id_bits = 0;  // bits of the largest gaussian id (0: two-array pairs)
+  if (allow_one_word)
+    for (int64_t v = n > 1 ? n - 1 : 0; v; v >>= 1) ++id_bits;
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, s, n_blocks, block_sums,
                      max_pairs, mt_bits, id_bits, dc);
   return hipGetLastError();

@@ -459,7 +459,8 @@ int higs_bin_sort(higs_ctx* c, void* stream) {
   {
     TimerScope ts(c, HIGS_TIMER_SCAN, s);
     rc = hip_err(launch_scan(c->n > 0 ? c->n : 0, c->f_cnt, c->block_sums,
-                             (uint32_t)c->max_pairs, n_bits((uint32_t)(c->n_mt - 1)), c->dc, s));
+                             (uint32_t)c->max_pairs, n_bits((uint32_t)(c->n_mt - 1)),
+                             (c->debug_flags & HIGS_DEBUG_TWO_WORD_PAIRS) == 0, c->dc, s));
   }
   if (rc) return rc;
   {

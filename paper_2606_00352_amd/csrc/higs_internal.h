@@ -115,7 +115,7 @@ hipError_t launch_project(int64_t n, const float* means, const float* scales, co
                           bool all_fields, hipStream_t s);
 
 hipError_t launch_scan(int64_t n, const uint32_t* cnt, uint32_t* block_sums, uint32_t max_pairs,
-                       int mt_bits, DeviceCounters* dc, hipStream_t s);
+                       int mt_bits, bool allow_one_word, DeviceCounters* dc, hipStream_t s);
 
 hipError_t launch_fill(int64_t n, CamArgs cam, const float* f_mx, const float* f_my,
                        const float* f_a, const float* f_b, const float* f_c, const float* f_tau,

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhigs.so")
 OK, E_INVALID, E_NOMEM, E_CAPACITY, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
 OVF_PAIRS, OVF_BATCHES = 1, 2
 DBG_PROJ, DBG_RECORDS, DBG_PAIRS, DBG_SORTED, DBG_MT_OFFSETS, DBG_BATCHES, DBG_ACTIVE, DBG_PARTIALS = range(1, 9)
-DEBUG_KEEP_PAIRS, DEBUG_COUNT_EVALS, DEBUG_PROJ_FIELDS = 1, 2, 4
+DEBUG_KEEP_PAIRS, DEBUG_COUNT_EVALS, DEBUG_PROJ_FIELDS, DEBUG_TWO_WORD_PAIRS = 1, 2, 4, 8
 SORT_SEGMENTED, SORT_ONESWEEP = 0, 1
 TIMER_NAMES = ("project", "scan", "fill", "sort", "batch", "raster", "merge")
 

@@ -14,7 +14,7 @@ def need_gpu():
         pytest.skip("no GPU")
 
 
-def gpu_frame(scene, cam, keep_pairs=True, ctx=None, **params):
+def gpu_frame(scene, cam, keep_pairs=True, ctx=None, debug=0, **params):
     """Renders one frame on the GPU; returns (ctx, image, T) with numpy outputs."""
     import torch
     from paper_2606_00352_amd import higs
@@ -24,7 +24,7 @@ def gpu_frame(scene, cam, keep_pairs=True, ctx=None, **params):
         ctx = higs.Context(n, cam.width, cam.height, max_pairs=max(64 * n, 1 << 16), **params)
     if keep_pairs:
         # every binning field stored too, for the projection's bit-exact check
-        ctx.set_debug(higs.DEBUG_KEEP_PAIRS | higs.DEBUG_PROJ_FIELDS)
+        ctx.set_debug(higs.DEBUG_KEEP_PAIRS | higs.DEBUG_PROJ_FIELDS | debug)
     t = higs.scene_tensors(scene)
     img, T = higs.render(ctx, t, cam)
     torch.cuda.synchronize()

@@ -18,9 +18,10 @@ pytestmark = pytest.mark.gpu
 SORT_MODES = pytest.mark.parametrize("sort_mode", [0, 1], ids=["segmented", "onesweep"])
 
 
-def _full_check(orc, scene, cam, cap=1024, report=None, check_partials=True, sort_mode=0):
+def _full_check(orc, scene, cam, cap=1024, report=None, check_partials=True, sort_mode=0,
+                debug=0):
     report = {} if report is None else report
-    ctx, img, T = gc.gpu_frame(scene, cam, batch_cap=cap, sort_mode=sort_mode)
+    ctx, img, T = gc.gpu_frame(scene, cam, batch_cap=cap, sort_mode=sort_mode, debug=debug)
     prm = gc.oracle_params(orc, batch_cap=cap)
     fr = orc.frame(scene, cam, prm)
     gc.check_projection(orc, ctx, fr, report)
@@ -257,6 +258,53 @@ def test_sort_modes_give_identical_frames(orc):
     for mode in (0, 1):
         ctx, img, T = gc.gpu_frame(sc, cam, sort_mode=mode)
         out.append((ctx.sorted_pairs(), ctx.batches(), img, T))
+    (k0, v0), b0, i0, t0 = out[0]
+    (k1, v1), b1, i1, t1 = out[1]
+    assert np.array_equal(k0, k1) and np.array_equal(v0, v1) and np.array_equal(b0, b1)
+    assert np.array_equal(i0, i1) and np.array_equal(t0, t1)
+
+
+def _tie_scene():
+    rng = np.random.default_rng(2)
+    n = 2000
+    sc = scenes.uniform_scene(n, seed=12)
+    sc.means[:, 2] = 3.0
+    sc.means[:, :2] = rng.uniform(-0.5, 0.5, (n, 2))
+    return sc, scenes.camera_at_origin(160, 160, 160.0)
+
+
+def _dense_scene():
+    n = 9000
+    sc = scenes.uniform_scene(n, seed=21)
+    rng = np.random.default_rng(21)
+    z = rng.uniform(2, 6, n).astype(np.float32)
+    sc.means[:, 0] = rng.uniform(-20, 20, n) * z / 256.0
+    sc.means[:, 1] = rng.uniform(-10, 10, n) * z / 256.0
+    sc.means[:, 2] = z
+    sc.scales[:] = 0.004
+    return sc, scenes.camera_at_origin(256, 128, 256.0)
+
+
+def _config0_scene():
+    sc, cams = scenes.config0()
+    return sc, cams[0]
+
+
+@pytest.mark.parametrize("make", [_config0_scene, _dense_scene, _tie_scene],
+                         ids=["config0", "dense", "ties"])
+def test_two_array_pairs(orc, make):
+    """The onesweep with key and id in separate arrays (the layout of frames
+    whose key and id do not fit one word), forced by a debug flag: every stage
+    against the oracle, and the same pairs, batches and image as the one-word
+    layout of the same frame."""
+    from paper_2606_00352_amd import higs
+    sc, cam = make()
+    out = []
+    for debug, pair_bytes in ((higs.DEBUG_TWO_WORD_PAIRS, 12), (0, 8)):
+        ctx, _ = _full_check(orc, sc, cam, sort_mode=1, debug=debug)
+        assert ctx.counts().sort_pair_bytes == pair_bytes
+        img, T = higs.render(ctx, higs.scene_tensors(sc), cam)
+        out.append((ctx.sorted_pairs(), ctx.batches(), img.cpu().numpy(), T.cpu().numpy()))
     (k0, v0), b0, i0, t0 = out[0]
     (k1, v1), b1, i1, t1 = out[1]
     assert np.array_equal(k0, k1) and np.array_equal(v0, v1) and np.array_equal(b0, b1)
