@@ -53,7 +53,7 @@ MEASURED_TRAFFIC = {
               "bytes_per_launch": 1514592617},
     "project": {"src_sha256": "ad7413dd2a7a1a520c87f852f1bdfbe8ca46679de393ea252e841c33580e4268",
                "bytes_per_launch": 1714746962},
-    "fill": {"src_sha256": "7512a00e46e7218273defd854560039b2ab3d60330bb6cfc331a8560d7e0a719",
+    "fill": {"src_sha256": "d8d983611e281dd798779a2a3dbeea5172af1bb04ca91953078bdd4ce5347190",
             "bytes_per_launch": 134195479},
     "sort": {"src_sha256": "12d8ca4f321840e5acceeec27b95f47ada7a83cd1313b625ebf8e5b924dd47ff",
             "bytes_per_launch": 917983361},

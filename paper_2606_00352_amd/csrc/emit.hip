@@ -1,21 +1,23 @@
 // Stage 2a: (macro-tile, gaussian) pair emission (sec. 3.2 and sec. 4.3:
 // count, prefix sum, fill).
 //
-// The per-gaussian counts come from the projection kernel.  `scan_kernel`
-// (one workgroup) turns the per-block sums into exclusive block offsets and
-// the frame's pair total; `fill_kernel` re-runs the intersection of each
-// gaussian from the stored float32 fields (so it takes the count pass's exact
-// decisions), scans the counts inside the block with wave prefix sums, and
-// writes pairs (key, value = gaussian id) in gaussian-id order, macro-tiles
-// ascending within a gaussian.  Waves whose 64 gaussians are all invisible
-// skip the fields entirely (ballot).
+// The per-gaussian counts and compact macro-tile lists (span words) come from
+// the projection kernel.  `scan_kernel` (one workgroup) turns the per-block
+// sums into exclusive block offsets and the frame's pair total, and chooses
+// the pair layout; `fill_kernel` scans the counts inside the block with wave
+// prefix sums and writes pairs in gaussian-id order, macro-tiles ascending
+// within a gaussian: each gaussian's macro-tiles come from its span word, or,
+// for a list the word cannot hold, from the intersection re-run on the stored
+// float32 fields (the count pass's exact decisions).  Waves whose 64 gaussians
+// are all invisible skip their work (ballot).
 //
 // Key layout: (macro-tile << dbits) | (depth bits - dmin), where dmin and
 // dmin + 2^dbits - 1 bracket the float32 depth bits of the frame's visible
 // gaussians (found by the projection).  The map is monotone in (macro-tile,
 // depth), so the sort order is unchanged, and the key has dbits + log2(n_mt)
-// significant bits instead of 32 + log2(n_mt): a 1080p frame over a depth range
-// of a few units sorts in five 8-bit passes rather than six.
+// significant bits instead of 32 + log2(n_mt).  A pair is the one word
+// key << g | id (g the id bits) when that fits 64 bits with a bit to spare,
+// else a key array and an id array.
 #include "higs_internal.h"
 #include "predicate.h"
 
