@@ -33,9 +33,12 @@ __device__ __forceinline__ uint32_t tile_overlap(float mx, float my, float l0, f
                                                  float tau, int tiles_x, int tiles_y) {
   const float taum = tau * 1.01f + 0.01f;
   const float st = sqrtf(taum);
-  const float ry = st / l2;
+  // reciprocals once per gaussian instead of divisions per tile row: their
+  // rounding (relative 1e-7) is far inside the margin on tau
+  const float inv_l0 = 1.0f / l0, inv_l2 = 1.0f / l2;
+  const float ry = st * inv_l2;
   const float s12 = sqrtf(l1 * l1 + l2 * l2);
-  const float dys = -l1 * st / (l2 * s12);
+  const float dys = -l1 * ry / s12;
   uint32_t mask = 0;
   for (int r = 0; r < tiles_y; ++r) {
     const float ya = (float)(r * kTile) + 0.5f - my;
@@ -46,8 +49,8 @@ __device__ __forceinline__ uint32_t tile_overlap(float mx, float my, float l0, f
     const float ym = fminf(fmaxf(-dys, dlo), dhi);
     const float sp = sqrtf(fmaxf(0.0f, taum - (l2 * yp) * (l2 * yp)));
     const float sm = sqrtf(fmaxf(0.0f, taum - (l2 * ym) * (l2 * ym)));
-    const float xp = mx + (sp - l1 * yp) / l0 + 0.5f;
-    const float xm = mx - (sm + l1 * ym) / l0 - 0.5f;
+    const float xp = mx + (sp - l1 * yp) * inv_l0 + 0.5f;
+    const float xm = mx - (sm + l1 * ym) * inv_l0 - 0.5f;
     // tile c spans pixel centres [8c + 0.5, 8c + 7.5]
     const float flo = fminf(fmaxf(ceilf((xm - 7.5f) * 0.125f), 0.0f), 8.0f);
     const float fhi = fminf(fmaxf(floorf((xp - 0.5f) * 0.125f), -1.0f), (float)(tiles_x - 1));
