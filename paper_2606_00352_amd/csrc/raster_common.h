@@ -32,13 +32,14 @@ struct RasterLds {
 __device__ __forceinline__ uint32_t tile_overlap(float mx, float my, float l0, float l1, float l2,
                                                  float tau, int tiles_x, int tiles_y) {
   const float taum = tau * 1.01f + 0.01f;
-  const float st = sqrtf(taum);
-  // reciprocals once per gaussian instead of divisions per tile row: their
-  // rounding (relative 1e-7) is far inside the margin on tau
-  const float inv_l0 = 1.0f / l0, inv_l2 = 1.0f / l2;
+  // the hardware square root, reciprocal and reciprocal square root (about
+  // one ulp each) instead of correctly rounded sequences, and reciprocals
+  // once per gaussian instead of divisions per tile row: these relative
+  // errors of ~1e-7 are far inside the margin on tau
+  const float st = __builtin_amdgcn_sqrtf(taum);
+  const float inv_l0 = __builtin_amdgcn_rcpf(l0), inv_l2 = __builtin_amdgcn_rcpf(l2);
   const float ry = st * inv_l2;
-  const float s12 = sqrtf(l1 * l1 + l2 * l2);
-  const float dys = -l1 * ry / s12;
+  const float dys = -l1 * ry * __builtin_amdgcn_rsqf(l1 * l1 + l2 * l2);
   uint32_t mask = 0;
   for (int r = 0; r < tiles_y; ++r) {
     const float ya = (float)(r * kTile) + 0.5f - my;
@@ -47,8 +48,8 @@ __device__ __forceinline__ uint32_t tile_overlap(float mx, float my, float l0, f
     if (!(dlo <= dhi)) continue;
     const float yp = fminf(fmaxf(dys, dlo), dhi);
     const float ym = fminf(fmaxf(-dys, dlo), dhi);
-    const float sp = sqrtf(fmaxf(0.0f, taum - (l2 * yp) * (l2 * yp)));
-    const float sm = sqrtf(fmaxf(0.0f, taum - (l2 * ym) * (l2 * ym)));
+    const float sp = __builtin_amdgcn_sqrtf(fmaxf(0.0f, taum - (l2 * yp) * (l2 * yp)));
+    const float sm = __builtin_amdgcn_sqrtf(fmaxf(0.0f, taum - (l2 * ym) * (l2 * ym)));
     const float xp = mx + (sp - l1 * yp) * inv_l0 + 0.5f;
     const float xm = mx - (sm + l1 * ym) * inv_l0 - 0.5f;
     // tile c spans pixel centres [8c + 0.5, 8c + 7.5]
