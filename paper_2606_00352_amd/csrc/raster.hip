@@ -9,7 +9,7 @@
 //     the Cholesky factors prescaled by sqrt(log2(e)/2) (so exp(-q/2) becomes
 //     one exp2), and tests it against the 32 render tiles with a conservative
 //     per-tile-row ellipse scan.  The per-gaussian 32-bit tile masks become
-//     per-tile 64-bit gaussian masks with 32 wave ballots (the transpose).
+//     per-tile 64-bit gaussian masks by a butterfly bit-matrix transpose.
 //   Queue: wave 0 ORs the masks per tile and compacts the active tiles.
 //   Phase 2: waves claim tiles from the queue through an LDS counter; a wave
 //     owns one 8x8 tile, one pixel per lane, walks the set bits of the tile's

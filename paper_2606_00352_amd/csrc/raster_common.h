@@ -111,8 +111,8 @@ __device__ __forceinline__ UnitInfo unit_info(const CamArgs& cam, const uint32_t
 // k = w, w + n_waves, ... (64 gaussians, one per lane), gathers the 48-byte
 // records by sorted id into LDS (macro-tile-relative, factors prescaled),
 // tests each gaussian against the render tiles and transposes the 32-bit
-// per-gaussian tile masks into 64-bit per-tile gaussian masks with 32
-// ballots.  Then wave 0 builds the queue of tiles with any gaussian and
+// per-gaussian tile masks into 64-bit per-tile gaussian masks (a butterfly
+// bit-matrix transpose).  Then wave 0 builds the queue of tiles with any gaussian and
 // returns their mask (in lane 0 of wave 0).  Ends with a barrier.
 template <int kWavesPerGroup>
 __device__ __forceinline__ uint32_t stage_unit(RasterLds& L, const UnitInfo& I,
@@ -134,13 +134,26 @@ __device__ __forceinline__ uint32_t stage_unit(RasterLds& L, const UnitInfo& I,
       L.gc[j] = make_float4(C.x, __builtin_amdgcn_logf(B.y), mxr, myr);  // b, log2 o, centre
       tmask = tile_overlap(mxr, myr, A.z, A.w, B.x, C.y, I.tiles_x, I.tiles_y);
     }
-    uint64_t mine = 0;
+    // the 64 x 32 bit matrix (lane = gaussian, bit = tile) transposed into
+    // 32 per-tile gaussian masks: a 32 x 32 bit transpose inside each half
+    // wave in five butterfly stages (stage j swaps the j-bit blocks that sit
+    // off the diagonal between lanes l and l ^ j: the partner's word rotated
+    // by j into place, then one bit-field insert), then lane t joins its word
+    // (gaussians 0..31 on tile t) with lane t + 32's (gaussians 32..63)
+    uint32_t x = tmask;
 #pragma unroll
-    for (int t = 0; t < kTilesPerMt; ++t) {
-      const uint64_t b = __ballot((tmask >> t) & 1u);
-      if (lane == t) mine = b;
+    for (int s = 0; s < 5; ++s) {
+      const int j = 16 >> s;
+      const uint32_t m = s == 0 ? 0x0000FFFFu : s == 1 ? 0x00FF00FFu : s == 2 ? 0x0F0F0F0Fu
+                       : s == 3 ? 0x33333333u : 0x55555555u;  // bits whose index has bit j clear
+      const bool upper = (lane & j) != 0;
+      const uint32_t y = (uint32_t)__shfl_xor((int)x, j, 64);
+      const uint32_t ys = __builtin_amdgcn_alignbit(y, y, upper ? j : 32 - j);  // rotate right
+      const uint32_t keep = upper ? ~m : m;
+      x = (x & keep) | (ys & ~keep);
     }
-    if (lane < kTilesPerMt) L.masks[k][lane] = mine;
+    const uint32_t x_hi = (uint32_t)__shfl_xor((int)x, 32, 64);
+    if (lane < kTilesPerMt) L.masks[k][lane] = ((uint64_t)x_hi << 32) | x;
   }
   __syncthreads();
   uint32_t act32 = 0;
