@@ -2,10 +2,12 @@
 // count, prefix sum, fill).
 //
 // The per-gaussian counts and compact macro-tile lists (span words) come from
-// the projection kernel.  `scan_kernel` (one workgroup) turns the per-block
-// sums into exclusive block offsets and the frame's pair total, and chooses
-// the pair layout; `fill_kernel` scans the counts inside the block with wave
-// prefix sums and writes pairs in gaussian-id order, macro-tiles ascending
+// the projection kernel.  `chunk_sum_kernel` sums the per-block sums over
+// chunks of kScanChunk blocks, `scan_kernel` (one workgroup) turns the chunk
+// totals into exclusive chunk offsets and the frame's pair total, and chooses
+// the pair layout; `fill_kernel` scans its chunk's block sums and the counts
+// inside the block with wave prefix sums and writes pairs in gaussian-id
+// order, macro-tiles ascending
 // within a gaussian: each gaussian's macro-tiles come from its span word, or,
 // for a list the word cannot hold, from the intersection re-run on the stored
 // float32 fields (the count pass's exact decisions).  Waves whose 64 gaussians
@@ -51,50 +53,53 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
   return v;
 }
 
-// One workgroup of 1024 threads: exclusive scan of the per-block (pairs,
-// visible) sums in place; writes the frame totals.  The sums are read in
-// chunks of 1024 x 16 blocks, each thread taking 16 consecutive blocks with
-// eight 16-byte loads (coalesced across the wave, all in flight at once); a
-// block-wide scan of the thread totals plus the carry of the earlier chunks
-// gives each thread its start.
+// A workgroup per chunk of kScanChunk projection blocks (a thread per block):
+// the chunk's (pairs, visible) totals, stored after the n_blocks block sums.
+__global__ void __launch_bounds__(kScanChunk)
+chunk_sum_kernel(uint32_t n_blocks, uint32_t* __restrict__ sums) {
+  __shared__ uint32_t wave_tot[2][kScanChunk / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t b = blockIdx.x * kScanChunk + threadIdx.x;
+  uint32_t p = b < n_blocks ? sums[2 * (size_t)b] : 0u;
+  uint32_t v = b < n_blocks ? sums[2 * (size_t)b + 1] : 0u;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    p += __shfl_xor(p, off, 64);
+    v += __shfl_xor(v, off, 64);
+  }
+  if (lane == 0) {
+    wave_tot[0][wave] = p;
+    wave_tot[1][wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tp = 0, tv = 0;
+#pragma unroll
+    for (int w = 0; w < kScanChunk / 64; ++w) {
+      tp += wave_tot[0][w];
+      tv += wave_tot[1][w];
+    }
+    sums[2 * (size_t)n_blocks + 2 * blockIdx.x] = tp;
+    sums[2 * (size_t)n_blocks + 2 * blockIdx.x + 1] = tv;
+  }
+}
+
+// One workgroup of 1024 threads: exclusive scan of the chunk totals of pairs
+// in place, the frame totals, and the pair layout.  A thread per chunk, chunks
+// in rounds of 1024 with the carry of the earlier rounds.
 constexpr int kScanThreads = 1024;
-constexpr int kScanPer = 16;  // blocks per thread per chunk
 __global__ void __launch_bounds__(kScanThreads)
-scan_kernel(uint32_t n_blocks, uint32_t* __restrict__ sums, uint32_t max_pairs, int mt_bits,
+scan_kernel(uint32_t n_chunks, uint32_t* __restrict__ chunk, uint32_t max_pairs, int mt_bits,
             int id_bits, DeviceCounters* __restrict__ dc) {
   __shared__ uint32_t wave_tot[2][kScanThreads / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t carry_p = 0, carry_v = 0;  // same in every thread
-  for (uint32_t c0 = 0; c0 < n_blocks; c0 += kScanThreads * kScanPer) {
-    const uint32_t b0 = c0 + threadIdx.x * kScanPer;
-    const bool full = b0 + kScanPer <= n_blocks;
-    uint32_t p[kScanPer], v[kScanPer];
-    if (full) {
-      const uint4* src = reinterpret_cast<const uint4*>(sums + 2 * (size_t)b0);
-#pragma unroll
-      for (int q = 0; q < kScanPer / 2; ++q) {
-        const uint4 x = src[q];
-        p[2 * q] = x.x;
-        v[2 * q] = x.y;
-        p[2 * q + 1] = x.z;
-        v[2 * q + 1] = x.w;
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < kScanPer; ++k) {
-        const uint32_t b = b0 + k;
-        p[k] = b < n_blocks ? sums[2 * (size_t)b] : 0u;
-        v[k] = b < n_blocks ? sums[2 * (size_t)b + 1] : 0u;
-      }
-    }
-    uint32_t sp = 0, sv = 0;
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-      sp += p[k];
-      sv += v[k];
-    }
-    const uint32_t ip = wave_incl_scan(sp);
-    const uint32_t iv = wave_incl_scan(sv);
+  for (uint32_t c0 = 0; c0 < n_chunks; c0 += kScanThreads) {
+    const uint32_t c = c0 + threadIdx.x;
+    const uint32_t p = c < n_chunks ? chunk[2 * (size_t)c] : 0u;
+    const uint32_t v = c < n_chunks ? chunk[2 * (size_t)c + 1] : 0u;
+    const uint32_t ip = wave_incl_scan(p);
+    const uint32_t iv = wave_incl_scan(v);
     if (lane == 63) {
       wave_tot[0][wave] = ip;
       wave_tot[1][wave] = iv;
@@ -107,26 +112,10 @@ scan_kernel(uint32_t n_blocks, uint32_t* __restrict__ sums, uint32_t max_pairs, 
       tot_p += wave_tot[0][w];
       tot_v += wave_tot[1][w];
     }
-    uint32_t run = base_p + ip - sp;
-    if (full) {
-      uint4* dst = reinterpret_cast<uint4*>(sums + 2 * (size_t)b0);
-#pragma unroll
-      for (int q = 0; q < kScanPer / 2; ++q) {
-        const uint32_t o0 = run;
-        const uint32_t o1 = run + p[2 * q];
-        run = o1 + p[2 * q + 1];
-        dst[q] = make_uint4(o0, v[2 * q], o1, v[2 * q + 1]);
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < kScanPer; ++k) {
-        if (b0 + k < n_blocks) sums[2 * (size_t)(b0 + k)] = run;
-        run += p[k];
-      }
-    }
+    if (c < n_chunks) chunk[2 * (size_t)c] = base_p + ip - p;
     carry_p += tot_p;
     carry_v += tot_v;
-    __syncthreads();  // wave_tot is rewritten by the next chunk
+    __syncthreads();  // wave_tot is rewritten by the next round
   }
   if (threadIdx.x == 0) {
     const uint32_t total = carry_p;
@@ -146,31 +135,45 @@ scan_kernel(uint32_t n_blocks, uint32_t* __restrict__ sums, uint32_t max_pairs, 
 hipError_t launch_scan(int64_t n, const uint32_t* cnt, uint32_t* block_sums, uint32_t max_pairs,
                        int mt_bits, bool allow_one_word, DeviceCounters* dc, hipStream_t s) {
   (void)cnt;
-  const uint32_t n_blocks = (uint32_t)((n + kProjBlock - 1) / kProjBlock);
+  const int64_t n_blocks = (n + kProjBlock - 1) / kProjBlock;
   int id_bits = 0;  // bits of the largest gaussian id (0: two-array pairs)
   if (allow_one_word)
     for (int64_t v = n > 1 ? n - 1 : 0; v; v >>= 1) ++id_bits;
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, s, n_blocks, block_sums,
-                     max_pairs, mt_bits, id_bits, dc);
+  const uint32_t n_chunks = (uint32_t)scan_chunks(n_blocks);
+  if (n_chunks > 0)
+    hipLaunchKernelGGL(chunk_sum_kernel, dim3(n_chunks), dim3(kScanChunk), 0, s,
+                       (uint32_t)n_blocks, block_sums);
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, s, n_chunks,
+                     block_sums + 2 * n_blocks, max_pairs, mt_bits, id_bits, dc);
   return hipGetLastError();
 }
 
 // One workgroup per kFillBlocks consecutive projection blocks (256 gaussians
 // each, one per thread per block): every count, span word and depth key of
-// the group is loaded first, then each block's pairs are written at its scan
-// offset plus the wave prefix sums.
+// the group is loaded first; the group's block offsets are its chunk's offset
+// plus a workgroup scan of the chunk's block sums (one per thread); then each
+// block's pairs are written at its offset plus the wave prefix sums.
 constexpr int kFillBlocks = 4;
+static_assert(kScanChunk == kProjBlock && kScanChunk % kFillBlocks == 0,
+              "one chunk block per fill thread; a fill group never straddles chunks");
 __global__ void __launch_bounds__(kProjBlock)
 fill_kernel(int64_t n, CamArgs cam, const float* __restrict__ f_mx, const float* __restrict__ f_my,
             const float* __restrict__ f_a, const float* __restrict__ f_b,
             const float* __restrict__ f_c, const float* __restrict__ f_tau,
             const uint32_t* __restrict__ f_key, const uint32_t* __restrict__ f_cnt,
-            const uint32_t* __restrict__ f_span, const uint32_t* __restrict__ block_offsets,
+            const uint32_t* __restrict__ f_span, const uint32_t* __restrict__ block_sums,
             uint32_t max_pairs, const DeviceCounters* __restrict__ dc,
             uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   __shared__ uint32_t wave_tot[kFillBlocks][kProjBlock / 64];
+  __shared__ uint32_t chunk_wave[kProjBlock / 64];
+  __shared__ uint32_t chunk_excl[kScanChunk];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t blk0 = (int64_t)blockIdx.x * kFillBlocks;
+  const int64_t n_blocks = (n + kProjBlock - 1) / kProjBlock;
+  const int64_t ch = blk0 / kScanChunk;
+  const int64_t cb = ch * kScanChunk + threadIdx.x;  // this thread's block of the chunk
+  const uint32_t cp = cb < n_blocks ? block_sums[2 * cb] : 0u;
+  const uint32_t chunk_base = block_sums[2 * n_blocks + 2 * ch];  // scanned chunk totals
   uint32_t cnt[kFillBlocks], span[kFillBlocks], key[kFillBlocks], incl[kFillBlocks];
 #pragma unroll
   for (int k = 0; k < kFillBlocks; ++k) {
@@ -180,15 +183,23 @@ fill_kernel(int64_t n, CamArgs cam, const float* __restrict__ f_mx, const float*
     span[k] = in ? f_span[i] : 0u;
     key[k] = in ? f_key[i] : 0u;
   }
-  const int64_t n_blocks = (n + kProjBlock - 1) / kProjBlock;
-  uint32_t boff[kFillBlocks];
+  // exclusive scan of the chunk's block pair counts
+  const uint32_t ci = wave_incl_scan(cp);
+  if (lane == 63) chunk_wave[wave] = ci;
 #pragma unroll
   for (int k = 0; k < kFillBlocks; ++k) {
-    boff[k] = blk0 + k < n_blocks ? block_offsets[2 * (blk0 + k)] : 0u;
     incl[k] = wave_incl_scan(cnt[k]);
     if (lane == 63) wave_tot[k][wave] = incl[k];
   }
   __syncthreads();
+  uint32_t ce = ci - cp;
+  for (int w = 0; w < wave; ++w) ce += chunk_wave[w];
+  chunk_excl[threadIdx.x] = ce;
+  __syncthreads();
+  uint32_t boff[kFillBlocks];
+#pragma unroll
+  for (int k = 0; k < kFillBlocks; ++k)
+    boff[k] = chunk_base + chunk_excl[blk0 + k - ch * kScanChunk];
   const uint32_t dmin = dc->key_min;
   const uint32_t dbits = depth_bits(dmin, dc->key_max);
   const uint32_t ish = dc->id_shift;
@@ -231,13 +242,13 @@ fill_kernel(int64_t n, CamArgs cam, const float* __restrict__ f_mx, const float*
 hipError_t launch_fill(int64_t n, CamArgs cam, const float* f_mx, const float* f_my,
                        const float* f_a, const float* f_b, const float* f_c, const float* f_tau,
                        const uint32_t* f_key, const uint32_t* f_cnt, const uint32_t* f_span,
-                       const uint32_t* block_offsets, uint32_t max_pairs,
+                       const uint32_t* block_sums, uint32_t max_pairs,
                        const DeviceCounters* dc, uint64_t* keys, uint32_t* vals, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t n_blocks = (n + kProjBlock - 1) / kProjBlock;
   const unsigned blocks = (unsigned)((n_blocks + kFillBlocks - 1) / kFillBlocks);
   hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(kProjBlock), 0, s, n, cam, f_mx, f_my, f_a,
-                     f_b, f_c, f_tau, f_key, f_cnt, f_span, block_offsets, max_pairs, dc, keys,
+                     f_b, f_c, f_tau, f_key, f_cnt, f_span, block_sums, max_pairs, dc, keys,
                      vals);
   return hipGetLastError();
 }

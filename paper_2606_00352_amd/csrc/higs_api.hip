@@ -236,7 +236,7 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
   rc |= dalloc(&c->f_cnt, G);
   rc |= dalloc(&c->f_span, G);
   rc |= dalloc(&c->rec, G);
-  rc |= dalloc(&c->block_sums, 2 * nblk);
+  rc |= dalloc(&c->block_sums, 2 * nblk + 2 * (size_t)scan_chunks((int64_t)nblk));
   rc |= dalloc(&c->keys[0], P);
   rc |= dalloc(&c->keys[1], P);
   rc |= dalloc(&c->vals[0], P);
@@ -290,7 +290,7 @@ int64_t higs_ctx_footprint(const higs_params* params, int64_t max_gaussians, int
   int64_t bytes = 0;
   bytes += G * (6 * 4 + 3 * 4);                // binning fields, key, count, span
   bytes += G * (int64_t)sizeof(RasterRecord);  // raster records
-  bytes += 2 * nblk * 4;                       // per-block sums
+  bytes += (2 * nblk + 2 * scan_chunks(nblk)) * 4;  // per-block and per-chunk sums
   bytes += P * (2 * 8 + 2 * 4);                // two key and two value buffers
   bytes += (int64_t)kMaxPasses * kRadix * 4 + ((int64_t)kMaxPasses + kMaxPasses * kRadix) * 4;
   bytes += tiles * kRadix * 8;                 // sort look-back words

@@ -19,6 +19,13 @@ constexpr int kTilesPerMt = kMtTilesX * kMtTilesY;  // 32
 constexpr int kMaxBatch = 1024;  // largest B_r the rasteriser's LDS holds
 
 constexpr int kProjBlock = 256;  // gaussians per projection / emission block
+// Projection blocks per scan chunk: a reduction writes each chunk's totals
+// after the n_blocks block sums, the scan runs over the chunk totals, and a
+// fill workgroup scans its chunk's block sums itself.
+constexpr int kScanChunk = 256;
+__host__ __device__ constexpr int64_t scan_chunks(int64_t n_blocks) {
+  return (n_blocks + kScanChunk - 1) / kScanChunk;
+}
 
 // Radix sort geometry.
 // 9-bit digits: a 1080p frame's keys (10 macro-tile bits, ~25 depth bits) take

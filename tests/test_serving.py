@@ -20,7 +20,8 @@ def test_context_footprint_counts_every_array():
     nblk = (G + 255) // 256
     tiles = (P + 6143) // 6144
     radix = 512                           # 9-bit sort digits
-    want = (G * (9 * 4 + 48) + 2 * nblk * 4 + P * 24 + 8 * radix * 4 + (8 + 8 * radix) * 4
+    nchunk = (nblk + 255) // 256          # scan chunks of 256 projection blocks
+    want = (G * (9 * 4 + 48) + 2 * nblk * 4 + 2 * nchunk * 4 + P * 24 + 8 * radix * 4 + (8 + 8 * radix) * 4
             + tiles * radix * 8
             + 2 * (n_mt + 1) * 4 + B * 16 + B * 32 * 64 * 16)
     got = higs.ctx_footprint(G, P, B, W, H)
