@@ -49,14 +49,14 @@ COPY_CALIBRATION_BYTES = 1 << 30
 MEASURED_TRAFFIC = {
     # profiles/frame_1080p_5p8m_hbm_traffic.md (sort: histogram + plan + every
     # onesweep dispatch of a frame)
-    "raster": {"src_sha256": "28c9f7b2d73087e16c4736844044b7043733df6cd7d90ebfa7713d186bffead4",
-              "bytes_per_launch": 1515017893},
-    "project": {"src_sha256": "ad7413dd2a7a1a520c87f852f1bdfbe8ca46679de393ea252e841c33580e4268",
-               "bytes_per_launch": 1714761325},
-    "fill": {"src_sha256": "d8d983611e281dd798779a2a3dbeea5172af1bb04ca91953078bdd4ce5347190",
-            "bytes_per_launch": 134202707},
-    "sort": {"src_sha256": "12d8ca4f321840e5acceeec27b95f47ada7a83cd1313b625ebf8e5b924dd47ff",
-            "bytes_per_launch": 904682699},
+    "raster": {"src_sha256": "161dccd743b80cb98af03ae9a466f6ce3b853b60ca831dd935f4efb9cc2966e3",
+              "bytes_per_launch": 1514840049},
+    "project": {"src_sha256": "db411b7566132f710396085286974f14bb354333c462ac24df2ee3478df62007",
+               "bytes_per_launch": 1714743639},
+    "fill": {"src_sha256": "1c2814b893dce0127c74d3691e143e1f611fb9c5075ccd12dba20e87f9014ce2",
+            "bytes_per_launch": 134935136},
+    "sort": {"src_sha256": "14e183273f7893df42277b8c779a1dd4212cbfc9bd491af5b974391978123fc5",
+            "bytes_per_launch": 921393734},
 }
 # the sources each figure depends on (the shared header holds the kernels' shapes)
 KERNEL_SOURCES = {"project": ("project.hip", "predicate.h", "higs_internal.h"),
