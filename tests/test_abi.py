@@ -103,3 +103,37 @@ def test_pair_overflow_is_reported_then_retry_succeeds(orc):
     higs.render(ctx3, t, cam)
     torch.cuda.synchronize()
     assert ctx3.counts().overflow == higs.OVF_BATCHES
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every struct the binding mirrors has the size and field offsets that a C
+    compiler gives the declaration in include/higs.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"higs_params": higs.Params, "higs_camera": higs.CameraC, "higs_counts": higs.Counts,
+               "higs_server_config": higs.ServerConfig, "higs_completion": higs.Completion,
+               "higs_server_stats": higs.ServerStats}
+    lines = ['#include <stdio.h>', '#include "higs.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'  printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        name, field, value = line.split()
+        got[(name, field)] = int(value)
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
