@@ -170,7 +170,7 @@ raster_backward_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ 
           const int j = __ffsll((unsigned long long)m) - 1;
           m &= m - 1ull;
           const int gi = k * 64 + j;
-          const float al = eval_alpha(L.ga[gi], L.gb[gi], L.gc[gi].y, pxr, pyr, amax).al;
+          const float al = eval_alpha(L.ga[gi], L.gb[gi], L.gb[gi].y, pxr, pyr, amax).al;
           if (T >= eps && al >= kAlphaMin) {
             T = fmaf(-al, T, T);  // the forward's update, bit for bit
             last = gi;
@@ -196,7 +196,7 @@ raster_backward_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ 
           const float4 B = L.gb[gi];
           const float4 C = L.gc[gi];
           const float bb = C.x;
-          const PixelEval ev = eval_alpha(A, B, C.y, pxr, pyr, amax);
+          const PixelEval ev = eval_alpha(A, B, B.y, pxr, pyr, amax);
           const bool take = gi <= last && ev.al >= kAlphaMin;
           if (__ballot(take) == 0) continue;
           float d0 = 0.0f, d1 = 0.0f, d2 = 0.0f, d3 = 0.0f, d4 = 0.0f, d5 = 0.0f, d6 = 0.0f,
@@ -214,7 +214,7 @@ raster_backward_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ 
             d7 = w * g1;
             d8 = w * g2;
             if (ev.e < amax) {  // alpha not clamped
-              d5 = dal * (ev.e / B.y);  // d alpha / d o = exp(-q/2); o > 0 for a listed gaussian
+              d5 = dal * (ev.e / C.y);  // d alpha / d o = exp(-q/2); o > 0 for a listed gaussian
               const float dq = -dal * ev.al * kLn2f;  // dL/dq'
               const float du = 2.0f * ev.u * dq, dv = 2.0f * ev.v * dq;
               const float dx = pxr - C.z, dy = pyr - C.w;  // pixel minus centre

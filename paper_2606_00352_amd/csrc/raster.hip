@@ -70,10 +70,9 @@ raster_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ vals0,
           m &= m - 1ull;
           const int gi = k * 64 + j;
           const float4 A = L.ga[gi];
-          const float4 B = L.gb[gi];
-          const float4 C = L.gc[gi];
-          const float bb = C.x;
-          const float al = eval_alpha(A, B, C.y, pxr, pyr, amax).al;
+          const float4 B = L.gb[gi];  // l2', log2 o, r, g
+          const float bb = L.gc[gi].x;
+          const float al = eval_alpha(A, B, B.y, pxr, pyr, amax).al;
           // branchless blend: a skipped gaussian adds w = 0 and keeps T
           // exactly; T(1 - a) is one fused T - aT, rounded once (the
           // adjoint's replay forms it the same way)

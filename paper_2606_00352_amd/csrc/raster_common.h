@@ -15,8 +15,8 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 struct RasterLds {
   float4 ga[kMaxBatch];  // c0 = l0' mx + l1' my, c1 = l2' my, l0', l1' (mx, my macro-tile relative)
-  float4 gb[kMaxBatch];  // l2', o, r, g
-  float4 gc[kMaxBatch];  // b, log2 o, mx, my (the stride of ga and gb: one address for all reads)
+  float4 gb[kMaxBatch];  // l2', log2 o, r, g
+  float4 gc[kMaxBatch];  // b, o, mx, my (the stride of ga and gb: one address for all reads)
   uint64_t masks[kMiniBatches][kTilesPerMt];
   uint32_t queue[kTilesPerMt];
   uint32_t qcount;
@@ -130,8 +130,8 @@ __device__ __forceinline__ uint32_t stage_unit(RasterLds& L, const UnitInfo& I,
       const float l0k = A.z * kSqrtHalfLog2e, l1k = A.w * kSqrtHalfLog2e;
       const float l2k = B.x * kSqrtHalfLog2e;
       L.ga[j] = make_float4(fmaf(l0k, mxr, l1k * myr), l2k * myr, l0k, l1k);
-      L.gb[j] = make_float4(l2k, B.y, B.z, B.w);
-      L.gc[j] = make_float4(C.x, __builtin_amdgcn_logf(B.y), mxr, myr);  // b, log2 o, centre
+      L.gb[j] = make_float4(l2k, __builtin_amdgcn_logf(B.y), B.z, B.w);  // l2', log2 o, r, g
+      L.gc[j] = make_float4(C.x, B.y, mxr, myr);                         // b, o, centre
       tmask = tile_overlap(mxr, myr, A.z, A.w, B.x, C.y, I.tiles_x, I.tiles_y);
     }
     // the 64 x 32 bit matrix (lane = gaussian, bit = tile) transposed into
