@@ -97,7 +97,7 @@ def lib():
             "oc_batches": (i64, [i64, P, i32, i32, P, P, i64]),
             "oc_render_untiled": (None, [i64, P, P, P, P, P, i64, P, P, P]),
             "oc_render_tiled": (None, [P, P, P, P, i64, P, P, P, i64, P, P, P]),
-            "oc_batch_partials": (None, [P, P, P, P, P, P]),
+            "oc_batch_partials": (None, [P, P, P, P, P, P, P]),
             "oc_sh_basis": (None, [P, ctypes.c_int, P]),
             "oc_depth_key": (ctypes.c_uint32, [ctypes.c_double]),
             "oc_num_threads": (ctypes.c_int, []),
@@ -106,6 +106,7 @@ def lib():
             "oc_render_tiled_grad": (None, [P, P, P, i64, P, P, P, P, P]),
             "oc_render_tiled_signature": (ctypes.c_uint64, [P, P, P, i64, P, P]),
             "oc_render_tiled_ambiguous": (i64, [i64, P, P, P, i64, P, P, P]),
+            "oc_alpha_flag_band": (None, [i64, P, P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -209,6 +210,21 @@ def batches(sorted_mt, n_mt: int, cap: int = 1024):
     return mt_off, tab[:nb]
 
 
+def alpha_flag_band(geo, gid, px, py):
+    """For evaluations k of gaussian gid[k] at pixel centre (px[k], py[k]):
+    (q, band, bound) -- the double q, the half-width of the band around tau
+    inside which the alpha decision is flagged ambiguous, and the float32
+    bound (oc_f32_q_bound) the band is built from."""
+    gid = np.ascontiguousarray(gid, dtype=np.int64)
+    px = np.ascontiguousarray(px, dtype=np.float64)
+    py = np.ascontiguousarray(py, dtype=np.float64)
+    n = gid.shape[0]
+    q, band, bound = (np.zeros(n, dtype=np.float64) for _ in range(3))
+    lib().oc_alpha_flag_band(n, _p(np.ascontiguousarray(geo)), _p(gid), _p(px), _p(py), _p(q), _p(band),
+                             _p(bound))
+    return q, band, bound
+
+
 def _pix(pixels):
     if pixels is None:
         return None, 0
@@ -251,15 +267,18 @@ def render_tiled(geo, sorted_gid, mt_off, tab, cam, params: Params = None, pixel
     return img, T, amb
 
 
-def batch_partials(geo, sorted_gid, batch_row, cam, params: Params = None) -> np.ndarray:
-    """[32 tiles, 64 px, 4] partial (R, G, B, T) of one batch from (0, 1)."""
+def batch_partials(geo, sorted_gid, batch_row, cam, params: Params = None, with_amb: bool = False):
+    """[32 tiles, 64 px, 4] partial (R, G, B, T) of one batch from (0, 1);
+    with_amb: also the [32, 64] ambiguity flags of those evaluations."""
     params = params or Params()
     out = np.zeros((MT_TILES, 64, 4), dtype=np.float64)
+    amb = np.zeros((MT_TILES, 64), dtype=np.uint8)
     row = np.ascontiguousarray(np.asarray(batch_row, dtype=np.int32).reshape(3))
     c, p = _cam(cam), params.c()
     sorted_gid = np.ascontiguousarray(sorted_gid, dtype=np.int32)
-    lib().oc_batch_partials(_p(geo), _p(sorted_gid), _p(row), ctypes.byref(c), ctypes.byref(p), _p(out))
-    return out
+    lib().oc_batch_partials(_p(geo), _p(sorted_gid), _p(row), ctypes.byref(c), ctypes.byref(p), _p(out),
+                            _p(amb))
+    return (out, amb) if with_amb else out
 
 
 @dataclasses.dataclass

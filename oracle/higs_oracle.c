@@ -413,15 +413,39 @@ double oc_f32_q_bound(const double* rec, double dx, double dy, double u, double 
   return 2.0 * fabs(u) * du + 2.0 * fabs(v) * dv + (q + 4.0) * 4.0 * e;
 }
 
-static double alpha_at(const double* rec, double px, double py, const oc_params* prm,
-                       uint8_t* amb) {
+/* Half-width of the band around tau inside which an alpha decision at pixel
+ * centre (px, py) is flagged: twice the float32 bound plus 1e-5 (1 + tau).
+ * *q_out receives the double q there. */
+static double flag_band(const double* rec, double px, double py, double* q_out) {
   double dx = px - rec[G_MX], dy = py - rec[G_MY];
   double u = rec[G_L0] * dx + rec[G_L1] * dy;
   double v = rec[G_L2] * dy;
   double q = u * u + v * v;
+  *q_out = q;
+  return 2.0 * oc_f32_q_bound(rec, dx, dy, u, v, q) + 1e-5 * (1.0 + rec[G_TAU]);
+}
+
+/* The band and q of flag_band for n (gaussian, pixel centre) evaluations;
+ * also the float32 bound alone (tests of the bound). */
+void oc_alpha_flag_band(int64_t n, const double* geo, const int64_t* gid, const double* px,
+                        const double* py, double* q, double* band, double* bound) {
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < n; ++k) {
+    const double* rec = geo + gid[k] * G_NCOL;
+    band[k] = flag_band(rec, px[k], py[k], &q[k]);
+    double dx = px[k] - rec[G_MX], dy = py[k] - rec[G_MY];
+    double u = rec[G_L0] * dx + rec[G_L1] * dy;
+    double v = rec[G_L2] * dy;
+    bound[k] = oc_f32_q_bound(rec, dx, dy, u, v, q[k]);
+  }
+}
+
+static double alpha_at(const double* rec, double px, double py, const oc_params* prm,
+                       uint8_t* amb) {
+  double q;
+  double band = flag_band(rec, px, py, &q);
   double tau = rec[G_TAU];
-  if (fabs(q - tau) <= 2.0 * oc_f32_q_bound(rec, dx, dy, u, v, q) + 1e-5 * (1.0 + tau))
-    *amb |= OC_AMB_ALPHA;
+  if (fabs(q - tau) <= band) *amb |= OC_AMB_ALPHA;
   double al = rec[G_OP] * exp(-0.5 * q);
   if (al > prm->alpha_max) al = prm->alpha_max;
   return al;
@@ -546,7 +570,8 @@ void oc_render_tiled(const double* geo, const int32_t* sorted_gid, const int64_t
  * ((ty*8 + tx)*64 + py*8 + px)), for stage-by-stage comparisons.  Pixels
  * outside the image get (0, 0, 0, 1). */
 void oc_batch_partials(const double* geo, const int32_t* sorted_gid, const int32_t* bt,
-                       const oc_camera* cam, const oc_params* prm, double* out /* 2048 x 4 */) {
+                       const oc_camera* cam, const oc_params* prm, double* out /* 2048 x 4 */,
+                       uint8_t* amb /* 2048 flags, or NULL */) {
   int32_t nmx = (cam->width + OC_MT_W - 1) / OC_MT_W;
   int32_t m = bt[0];
   int32_t x0 = (m % nmx) * OC_MT_W, y0 = (m / nmx) * OC_MT_H;
@@ -556,11 +581,13 @@ void oc_batch_partials(const double* geo, const int32_t* sorted_gid, const int32
       int32_t x = x0 + tx * OC_TILE + q % OC_TILE;
       int32_t y = y0 + ty * OC_TILE + q / OC_TILE;
       double* o = out + 4 * ((int64_t)t * 64 + q);
+      if (amb) amb[(int64_t)t * 64 + q] = 0;
       if (x >= cam->width || y >= cam->height) { o[0] = o[1] = o[2] = 0.0; o[3] = 1.0; continue; }
       double C[3], T;
       uint8_t a = 0;
       batch_partial(geo, sorted_gid, bt, x + 0.5, y + 0.5, prm, C, &T, &a);
       o[0] = C[0]; o[1] = C[1]; o[2] = C[2]; o[3] = T;
+      if (amb) amb[(int64_t)t * 64 + q] = a;
     }
   }
 }

@@ -5,6 +5,11 @@ import pytest
 
 IMG_MAX_ABS = 2e-4   # per channel, pixels not flagged ambiguous
 IMG_MEAN_ABS = 1e-5  # per channel, all pixels
+# Pixels the oracle may flag ambiguous (an alpha decided within the pinned
+# float32 band of 1/255, or a transmittance next to t_eps), as a fraction of
+# the compared pixels: ~0.1% on the parity scene, ~0.6% on a 1080p view of the
+# benchmark scene, where float32 centres near x = 1000 px widen the band.
+AMB_MAX_FRACTION = 0.01
 COLOUR_ABS = 2e-6    # float32 SH colour against the double oracle
 
 
@@ -107,6 +112,8 @@ def check_image(img, T, o_img, o_T, amb, report, cmax=None):
     d = np.abs(img.astype(np.float64) - o_img)
     clean = amb == 0
     report["ambiguous_pixels"] = int((~clean).sum())
+    report["ambiguous_fraction"] = float((~clean).mean()) if clean.size else 0.0
+    assert report["ambiguous_fraction"] <= AMB_MAX_FRACTION, report
     report["max_abs"] = float(d[clean].max()) if clean.any() else 0.0
     report["mean_abs"] = float(d.mean()) if d.size else 0.0
     if clean.any():
