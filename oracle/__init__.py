@@ -107,6 +107,8 @@ def lib():
             "oc_render_tiled_signature": (ctypes.c_uint64, [P, P, P, i64, P, P]),
             "oc_render_tiled_ambiguous": (i64, [i64, P, P, P, i64, P, P, P]),
             "oc_alpha_flag_band": (None, [i64, P, P, P, P, P, P, P]),
+            "oc_count_evals": (None, [P, P, P, i64, P, P, P]),
+            "oc_set_threads": (None, [ctypes.c_int]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -133,6 +135,11 @@ def _cam(cam) -> _Camera:
 
 def num_threads() -> int:
     return int(lib().oc_num_threads())
+
+
+def set_threads(n: int):
+    """Threads of the oracle's parallel loops from now on."""
+    lib().oc_set_threads(int(n))
 
 
 def n_macro_tiles(width: int, height: int):
@@ -223,6 +230,20 @@ def alpha_flag_band(geo, gid, px, py):
     lib().oc_alpha_flag_band(n, _p(np.ascontiguousarray(geo)), _p(gid), _p(px), _p(py), _p(q), _p(band),
                              _p(bound))
     return q, band, bound
+
+
+def count_evals(geo, sorted_gid, tab, cam, params: Params = None):
+    """(all, read): pixel-gaussian evaluations of the batched form -- over
+    every (unit, tile), and over the (unit, tile) pairs whose partial the
+    merge reads (oc_count_evals)."""
+    params = params or Params()
+    out = np.zeros(2, dtype=np.int64)
+    c, p = _cam(cam), params.c()
+    sorted_gid = np.ascontiguousarray(sorted_gid, dtype=np.int32)
+    tab = np.ascontiguousarray(tab, dtype=np.int32)
+    lib().oc_count_evals(_p(np.ascontiguousarray(geo)), _p(sorted_gid), _p(tab), tab.shape[0], ctypes.byref(c),
+                         ctypes.byref(p), _p(out))
+    return int(out[0]), int(out[1])
 
 
 def _pix(pixels):

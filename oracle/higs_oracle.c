@@ -565,6 +565,88 @@ void oc_render_tiled(const double* geo, const int32_t* sorted_gid, const int64_t
   free(first);
 }
 
+/* Pixel-gaussian evaluations the batched form needs (the rasteriser's work
+ * count).  Per (macro-tile, batch) unit and render tile, in the unit's depth
+ * order, a gaussian is evaluated at the tile's 64 pixels when its level
+ * ellipse {q <= tau} contains at least one of the tile's pixel centres (the
+ * per-tile visibility of Alg. 1, taken exactly), until every in-image pixel
+ * of the tile has local T < t_eps (the unanimous early-out of Alg. 2).
+ *   out[0] = 64 x those evaluations over every unit and tile;
+ *   out[1] = the same over the (unit, tile) pairs whose partial the merge of
+ *            Eq. 1 reads: some in-image pixel of the tile still has merged
+ *            T >= t_eps before the batch (the product of the earlier batches'
+ *            partial T, taken while it is >= t_eps).
+ * The second is the work a rasteriser that skips tiles the earlier batches
+ * have saturated must do at least. */
+void oc_count_evals(const double* geo, const int32_t* sorted_gid, const int32_t* batch_tab,
+                    int64_t nbatches, const oc_camera* cam, const oc_params* prm, int64_t out[2]) {
+  int32_t nmx = (cam->width + OC_MT_W - 1) / OC_MT_W;
+  int32_t nmy = (cam->height + OC_MT_H - 1) / OC_MT_H;
+  int32_t nmt = nmx * nmy;
+  int64_t* first = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nmt + 1));
+  for (int32_t m = 0; m <= nmt; ++m) first[m] = nbatches;
+  for (int64_t bi = nbatches - 1; bi >= 0; --bi) first[batch_tab[3 * bi]] = bi;
+  for (int32_t m = nmt - 1; m >= 0; --m)
+    if (first[m] > first[m + 1]) first[m] = first[m + 1];
+  int64_t all = 0, read = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : all, read)
+  for (int32_t m = 0; m < nmt; ++m) {
+    int32_t x0 = (m % nmx) * OC_MT_W, y0 = (m / nmx) * OC_MT_H;
+    double Tm[OC_MT_TX * OC_MT_TY][64];
+    for (int t = 0; t < OC_MT_TX * OC_MT_TY; ++t)
+      for (int p = 0; p < 64; ++p) Tm[t][p] = 1.0;
+    for (int64_t bi = first[m]; bi < first[m + 1]; ++bi) {
+      const int32_t* bt = batch_tab + 3 * bi;
+      for (int t = 0; t < OC_MT_TX * OC_MT_TY; ++t) {
+        int32_t tx0 = x0 + (t % OC_MT_TX) * OC_TILE, ty0 = y0 + (t / OC_MT_TX) * OC_TILE;
+        if (tx0 >= cam->width || ty0 >= cam->height) continue;
+        int inside[64];
+        int merge_reads = 0;
+        for (int p = 0; p < 64; ++p) {
+          inside[p] = (tx0 + p % OC_TILE) < cam->width && (ty0 + p / OC_TILE) < cam->height;
+          if (inside[p] && Tm[t][p] >= prm->t_eps) merge_reads = 1;
+        }
+        double T[64];
+        for (int p = 0; p < 64; ++p) T[p] = 1.0;
+        int64_t cnt = 0;
+        for (int32_t k = 0; k < bt[2]; ++k) {
+          int live = 0;
+          for (int p = 0; p < 64; ++p) live |= inside[p] && T[p] >= prm->t_eps;
+          if (!live) break;
+          const double* rec = geo + (int64_t)sorted_gid[bt[1] + k] * G_NCOL;
+          double tau = rec[G_TAU];
+          /* the ellipse's bounding box against the tile's pixel centres first */
+          double ex = sqrt(tau * rec[G_A]), ey = sqrt(tau * rec[G_C]);
+          if (rec[G_MX] + ex < tx0 + 0.5 || rec[G_MX] - ex > tx0 + 7.5 || rec[G_MY] + ey < ty0 + 0.5 ||
+              rec[G_MY] - ey > ty0 + 7.5)
+            continue;
+          int hit = 0;
+          for (int p = 0; p < 64; ++p) {
+            double dx = tx0 + p % OC_TILE + 0.5 - rec[G_MX], dy = ty0 + p / OC_TILE + 0.5 - rec[G_MY];
+            double u = rec[G_L0] * dx + rec[G_L1] * dy, v = rec[G_L2] * dy;
+            double q = u * u + v * v;
+            if (q > tau) continue;
+            hit = 1;
+            if (T[p] < prm->t_eps) continue;
+            double al = rec[G_OP] * exp(-0.5 * q);
+            if (al > prm->alpha_max) al = prm->alpha_max;
+            if (al < prm->alpha_min) continue;
+            T[p] = T[p] * (1.0 - al);
+          }
+          cnt += hit;
+        }
+        all += 64 * cnt;
+        if (merge_reads) read += 64 * cnt;
+        for (int p = 0; p < 64; ++p)
+          if (Tm[t][p] >= prm->t_eps) Tm[t][p] = Tm[t][p] * T[p];
+      }
+    }
+  }
+  free(first);
+  out[0] = all;
+  out[1] = read;
+}
+
 /* Per-pixel partial (C, T) of one batch over the 32 render tiles x 64 pixels
  * of its macro-tile (pixel (tx*8 + px, ty*8 + py) of the macro-tile at index
  * ((ty*8 + tx)*64 + py*8 + px)), for stage-by-stage comparisons.  Pixels
@@ -590,6 +672,15 @@ void oc_batch_partials(const double* geo, const int32_t* sorted_gid, const int32
       if (amb) amb[(int64_t)t * 64 + q] = a;
     }
   }
+}
+
+/* Threads of the oracle's parallel loops (timing its single-core rate). */
+void oc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
 }
 
 int oc_num_threads(void) {
