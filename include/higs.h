@@ -40,9 +40,13 @@
  *   - Return value: HIGS_OK (0) or a negative HIGS_E_* code; higs_error_string
  *     turns it into text.  Data-dependent capacity overflow (more pairs or
  *     batches than the context holds) cannot be known when the work is
- *     enqueued: it is recorded on the device, the outputs of that frame are
- *     then undefined, and higs_get_counts reports it (overflow bits) so the
- *     caller can grow the context and render again.
+ *     enqueued: it is recorded on the device and the frame stops there —
+ *     every later kernel of the frame returns at once, the image and T_out
+ *     are filled with NaN, and higs_raster_backward writes NaN gradients.
+ *     higs_get_counts reports it (overflow bits, and the number of pairs the
+ *     frame asked for; after a pair overflow the batch stage does not run and
+ *     the batch count is 0) so the caller can grow the context and render
+ *     again.
  *   - Gaussians with a non-finite mean, scale, rotation or opacity, a zero
  *     quaternion, camera-space depth <= near_z, opacity below 1/255, or a
  *     non-positive-definite 2D covariance are culled (not an error).
@@ -202,7 +206,7 @@ int higs_render(higs_ctx* ctx, int64_t n, const float* means, const float* scale
  * results vary in the last bits from run to run.  Needs a completed
  * higs_raster on ctx since its last higs_project (else HIGS_E_STATE); the
  * first call allocates the adjoint's buffers (max_batches * 16 KiB +
- * max_gaussians * 64 B; HIGS_E_NOMEM if that fails).  Outputs are undefined
+ * max_gaussians * 64 B; HIGS_E_NOMEM if that fails).  Every gradient is NaN
  * when the frame overflowed its capacities (higs_get_counts). */
 int higs_raster_backward(higs_ctx* ctx, const float* dL_dimage, const float* dL_dT,
                          float* dmeans, float* dscales, float* dquats, float* dopacities,
@@ -238,7 +242,7 @@ typedef struct {
 typedef struct {
   int64_t request_id;
   float gpu_ms;       /* device time of the frame, events on its stream */
-  uint32_t overflow;  /* HIGS_OVF_* bits of the frame (its image is then undefined) */
+  uint32_t overflow;  /* HIGS_OVF_* bits of the frame (its image is then NaN) */
   int32_t cls;
 } higs_completion;
 

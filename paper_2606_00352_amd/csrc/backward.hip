@@ -66,7 +66,7 @@ merge_backward_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ b
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const uint32_t mt = (uint32_t)((ty / kMtTilesY) * cam.n_mt_x + tx / kMtTilesX);
   const uint32_t t = (uint32_t)((ty % kMtTilesY) * kMtTilesX + tx % kMtTilesX);
-  const uint32_t nb = dc->n_batches;
+  const uint32_t nb = dc->overflow ? 0u : dc->n_batches;  // no batches after an overflow
   const uint32_t b0 = min(batch_first[mt], nb), b1 = min(batch_first[mt + 1], nb);
   const int x = tx * kTile + (lane & 7), y = ty * kTile + (lane >> 3);
   float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, gT = 0.0f;
@@ -127,6 +127,7 @@ raster_backward_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ 
                        const float2* __restrict__ state, const float* __restrict__ dimg,
                        float* __restrict__ dgeo) {
   __shared__ RasterLds L;
+  if (dc->overflow) return;  // the frame stopped at a capacity overflow
   const uint32_t* __restrict__ sorted = dc->sort_final ? vals1 : vals0;
   const uint32_t n_units = dc->n_batches;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -320,18 +321,22 @@ project_backward_kernel(int64_t n, const float* __restrict__ means, const float*
                         const float* __restrict__ quats, const float* __restrict__ sh, CamArgs cam,
                         ParamArgs prm, float3 campos, const uint32_t* __restrict__ f_cnt,
                         const RasterRecord* __restrict__ rec, const float* __restrict__ dgeo,
-                        float* __restrict__ dmeans, float* __restrict__ dscales,
-                        float* __restrict__ dquats, float* __restrict__ dopac,
-                        float* __restrict__ dsh) {
+                        const DeviceCounters* __restrict__ dc, float* __restrict__ dmeans,
+                        float* __restrict__ dscales, float* __restrict__ dquats,
+                        float* __restrict__ dopac, float* __restrict__ dsh) {
   const int64_t i = (int64_t)blockIdx.x * kProjBwdBlock + threadIdx.x;
   if (i >= n) return;
   const int ncoef = (prm.sh_degree + 1) * (prm.sh_degree + 1);
   float* gsh = dsh + (int64_t)ncoef * 3 * i;
-  if (f_cnt[i] == 0) {  // culled or off-screen: no pixel depends on it
-    for (int k = 0; k < 3; ++k) dmeans[3 * i + k] = dscales[3 * i + k] = 0.0f;
-    for (int k = 0; k < 4; ++k) dquats[4 * i + k] = 0.0f;
-    for (int k = 0; k < ncoef * 3; ++k) gsh[k] = 0.0f;
-    dopac[i] = 0.0f;
+  // culled or off-screen: no pixel depends on it (0); after a capacity
+  // overflow the frame has no gradient (NaN)
+  const bool ovf = dc->overflow != 0;
+  if (ovf || f_cnt[i] == 0) {
+    const float z = ovf ? __builtin_nanf("") : 0.0f;
+    for (int k = 0; k < 3; ++k) dmeans[3 * i + k] = dscales[3 * i + k] = z;
+    for (int k = 0; k < 4; ++k) dquats[4 * i + k] = z;
+    for (int k = 0; k < ncoef * 3; ++k) gsh[k] = z;
+    dopac[i] = z;
     return;
   }
   const float* gr = dgeo + (size_t)i * kGradStride;
@@ -552,8 +557,8 @@ hipError_t launch_backward(int64_t n, const float* means, const float* scales, c
     campos.z = -(cam.R[2] * cam.t[0] + cam.R[5] * cam.t[1] + cam.R[8] * cam.t[2]);
     const unsigned pblocks = (unsigned)((n + kProjBwdBlock - 1) / kProjBwdBlock);
     hipLaunchKernelGGL(project_backward_kernel, dim3(pblocks), dim3(kProjBwdBlock), 0, s, n, means,
-                       scales, quats, sh, cam, prm, campos, f_cnt, rec, dgeo, dmeans, dscales,
-                       dquats, dopac, dsh);
+                       scales, quats, sh, cam, prm, campos, f_cnt, rec, dgeo, dc, dmeans,
+                       dscales, dquats, dopac, dsh);
   }
   return hipGetLastError();
 }

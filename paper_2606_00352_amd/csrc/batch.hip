@@ -18,7 +18,7 @@ __global__ void __launch_bounds__(kOffThreads)
 mt_offsets_kernel(int n_mt, const uint64_t* __restrict__ k0, const uint64_t* __restrict__ k1,
                   const DeviceCounters* __restrict__ dc, uint32_t* __restrict__ mt_off) {
   const int m = blockIdx.x * (kOffThreads / 64) + (threadIdx.x >> 6);
-  if (m > n_mt) return;
+  if (m > n_mt || dc->overflow) return;
   const int lane = threadIdx.x & 63;
   const uint64_t* __restrict__ keys = dc->sort_final ? k1 : k0;
   // keys are macro-tile << d | depth, shifted above the id in one-word pairs
@@ -50,6 +50,7 @@ batch_table_kernel(int n_mt, uint32_t cap, uint32_t max_batches, const uint32_t*
                    DeviceCounters* __restrict__ dc, uint32_t* __restrict__ batch_first,
                    uint32_t* __restrict__ tab) {
   __shared__ uint32_t wave_tot[kBtThreads / 64];
+  if (dc->overflow) return;  // pairs were cut: no batch table for this frame
   const int per = (n_mt + kBtThreads - 1) / kBtThreads;
   const int m0 = threadIdx.x * per;
   const int m1 = min(m0 + per, n_mt);
@@ -83,9 +84,9 @@ batch_table_kernel(int n_mt, uint32_t cap, uint32_t max_batches, const uint32_t*
 __global__ void __launch_bounds__(kOffThreads)
 batch_rows_kernel(int n_mt, uint32_t cap, uint32_t max_batches,
                   const uint32_t* __restrict__ mt_off, const uint32_t* __restrict__ batch_first,
-                  uint32_t* __restrict__ tab) {
+                  const DeviceCounters* __restrict__ dc, uint32_t* __restrict__ tab) {
   const int m = blockIdx.x * (kOffThreads / 64) + (threadIdx.x >> 6);
-  if (m >= n_mt) return;
+  if (m >= n_mt || dc->overflow) return;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t off = mt_off[m];
   const uint32_t len = mt_off[m + 1] - off;
@@ -110,7 +111,7 @@ static void launch_table(int n_mt, uint32_t batch_cap, uint32_t max_batches, Dev
   const int row_blocks = (n_mt + (kOffThreads / 64) - 1) / (kOffThreads / 64);
   if (row_blocks > 0)
     hipLaunchKernelGGL(batch_rows_kernel, dim3(row_blocks), dim3(kOffThreads), 0, s, n_mt,
-                       batch_cap, max_batches, mt_off, batch_first, batch_tab);
+                       batch_cap, max_batches, mt_off, batch_first, dc, batch_tab);
 }
 
 hipError_t launch_batch(int n_mt, uint32_t batch_cap, uint32_t max_batches, const uint64_t* const* keys2,

@@ -167,6 +167,7 @@ fill_kernel(int64_t n, CamArgs cam, const float* __restrict__ f_mx, const float*
   __shared__ uint32_t wave_tot[kFillBlocks][kProjBlock / 64];
   __shared__ uint32_t chunk_wave[kProjBlock / 64];
   __shared__ uint32_t chunk_excl[kScanChunk];
+  if (dc->overflow) return;  // the frame stops at a capacity overflow
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t blk0 = (int64_t)blockIdx.x * kFillBlocks;
   const int64_t n_blocks = (n + kProjBlock - 1) / kProjBlock;

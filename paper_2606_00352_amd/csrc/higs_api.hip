@@ -72,6 +72,21 @@ struct higs_ctx {
 
 namespace {
 
+// Fills n 64-bit words with zero (a kernel, so that a caller capturing the
+// stream into a graph records no memset node).
+__global__ void zero_words_kernel(uint64_t* __restrict__ p, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0ull;
+}
+
+hipError_t launch_zero_words(uint64_t* p, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t want = (n + 255) / 256;
+  hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)(want < 2048 ? want : 2048)), dim3(256), 0,
+                     s, p, n);
+  return hipGetLastError();
+}
+
 struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int dev) {
@@ -487,8 +502,15 @@ int higs_bin_sort(higs_ctx* c, void* stream) {
                              c->n_cus, s));
   }
   c->epoch += (uint32_t)c->n_passes;
-  if (c->epoch >= (1u << 30) - 64) c->epoch = 1;  // status words hold 30 epoch bits
   if (rc) return rc;
+  if (c->epoch >= (1u << 30) - 64) {
+    // status words hold 30 epoch bits: before the epochs start again at 1,
+    // every word goes back to untagged, so that no word of an early frame
+    // can pass for one published by a later pass with the same epoch
+    c->epoch = 1;
+    rc = hip_err(launch_zero_words(c->status, (size_t)c->max_tiles * kRadix, s));
+    if (rc) return rc;
+  }
   c->stage = 2;
   return HIGS_OK;
 }

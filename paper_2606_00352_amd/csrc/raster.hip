@@ -36,6 +36,7 @@ raster_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ vals0,
               const uint32_t* __restrict__ batch_tab, DeviceCounters* __restrict__ dc,
               float4* __restrict__ partials, uint32_t* __restrict__ active) {
   __shared__ RasterLds L;
+  if (dc->overflow) return;  // the frame stops at a capacity overflow
   const uint32_t* __restrict__ sorted = dc->sort_final ? vals1 : vals0;
   const uint32_t n_units = dc->n_batches;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -108,7 +109,7 @@ merge_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ batch_firs
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const uint32_t mt = (uint32_t)((ty / kMtTilesY) * cam.n_mt_x + tx / kMtTilesX);
   const uint32_t t = (uint32_t)((ty % kMtTilesY) * kMtTilesX + tx % kMtTilesX);
-  const uint32_t nb = dc->n_batches;
+  const uint32_t nb = dc->overflow ? 0u : dc->n_batches;
   const uint32_t b0 = min(batch_first[mt], nb), b1 = min(batch_first[mt + 1], nb);
   const float eps = prm.t_eps;
   float cr = 0.0f, cg = 0.0f, cb = 0.0f, T = 1.0f;
@@ -149,6 +150,9 @@ merge_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ batch_firs
     }
   }
   const int x = tx * kTile + (lane & 7), y = ty * kTile + (lane >> 3);
+  if (dc->overflow) {  // no partials were made: the image says so
+    cr = cg = cb = T = __builtin_nanf("");
+  }
   if (x < cam.width && y < cam.height) {
     const size_t pix = (size_t)y * cam.width + x;
     image[3 * pix + 0] = cr + T * cam.bg[0];

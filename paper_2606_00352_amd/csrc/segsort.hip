@@ -164,6 +164,7 @@ seg_fill_kernel(int64_t n, CamArgs cam, int n_mt, uint32_t gbits, const float* _
                 const DeviceCounters* __restrict__ dc, uint32_t max_pairs,
                 uint64_t* __restrict__ comp) {
   HIP_DYNAMIC_SHARED(uint32_t, lds)
+  if (dc->overflow) return;  // the frame stops at a capacity overflow
   uint32_t* cnt = lds;          // hits of this batch per macro-tile, then the running slot
   uint32_t* base = lds + n_mt;  // reserved start of this batch's range in each segment
   for (int m = threadIdx.x; m < n_mt; m += kSegThreads) cnt[m] = 0;
@@ -249,6 +250,7 @@ seg_chunk_sort_kernel(int n_mt, uint32_t gbits, const uint32_t* __restrict__ mt_
                       DeviceCounters* __restrict__ dc) {
   HIP_DYNAMIC_SHARED(uint64_t, v)
   __shared__ uint32_t s_chunk;
+  if (dc->overflow) return;
   const uint32_t total = chunk_off[n_mt];
   const uint32_t np = dc->n_pairs;
   const uint64_t idmask = (1ull << gbits) - 1ull;
@@ -304,6 +306,7 @@ seg_merge_kernel(int level, int n_mt, uint32_t gbits, const uint32_t* __restrict
   __shared__ uint32_t s_blk;
   const uint64_t run = (uint64_t)kChunk << level;
   if ((uint64_t)dc->seg_max <= run) return;  // every segment was finished before this level
+  if (dc->overflow) return;
   const uint32_t total = blk_off[n_mt];
   const uint32_t np = dc->n_pairs;
   const uint64_t idmask = (1ull << gbits) - 1ull;

@@ -46,6 +46,7 @@ sort_hist_kernel(const uint64_t* __restrict__ keys, const DeviceCounters* __rest
   // the top digits of a frame's keys take few values: spreading the counters
   // over copies keeps the LDS atomics of one wave from piling on one address
   __shared__ uint32_t h[kHistCopies][kMaxPasses * kRadix];
+  if (dc->overflow) return;  // the frame stops at a capacity overflow
   const uint32_t n = dc->n_pairs;
   const uint32_t ish = dc->id_shift;  // key bits start above the id in a one-word pair
   // digit positions above the frame's key width are zero in every key
@@ -88,6 +89,7 @@ __global__ void __launch_bounds__(kRadix)
 sort_plan_kernel(const uint32_t* __restrict__ hist, DeviceCounters* __restrict__ dc, int n_passes,
                  int mt_bits, uint32_t* __restrict__ plan, uint32_t* __restrict__ base) {
   __shared__ uint32_t wave_tot[kRadix / 64];
+  if (dc->overflow) return;
   const uint32_t n = dc->n_pairs;
   const int np = (mt_bits + (int)depth_bits(dc->key_min, dc->key_max) + kRadixBits - 1) / kRadixBits;
   const int d = threadIdx.x, lane = d & 63, wave = d >> 6;
@@ -153,6 +155,7 @@ onesweep_kernel(int pass, uint32_t epoch, uint64_t* __restrict__ k0, uint32_t* _
                 const uint32_t* __restrict__ plan, const uint32_t* __restrict__ base,
                 uint64_t* __restrict__ status, DeviceCounters* __restrict__ dc) {
   __shared__ SortLds L;
+  if (dc->overflow) return;  // (the plan was not written either)
   const uint32_t src = plan[pass];
   if (src == 0xffffffffu) return;  // every key has the same digit: identity pass
   const uint64_t* __restrict__ kin = src ? k1 : k0;
@@ -208,6 +211,10 @@ onesweep_kernel(int pass, uint32_t epoch, uint64_t* __restrict__ k0, uint32_t* _
       const uint32_t before = (uint32_t)__popcll(peers & lt_mask);
       const uint32_t prev = L.whist[wave][d];
       rank[k] = prev + before;
+      // every lane of the wave has read its digit's count before the first
+      // lane of each digit group adds the group to it (the wave executes in
+      // lockstep; the barrier keeps the compiler from moving the store up)
+      __builtin_amdgcn_wave_barrier();
       if (before == 0) L.whist[wave][d] = prev + (uint32_t)__popcll(peers);
     }
     __syncthreads();

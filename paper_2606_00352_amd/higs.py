@@ -169,6 +169,16 @@ def _stream(stream):
     return stream.cuda_stream
 
 
+class CapacityError(HigsError):
+    """A frame needed more pairs or batches than its context holds (the
+    library stops such a frame on the device: NaN image, no gradients)."""
+
+    def __init__(self, counts):
+        self.counts = counts
+        super().__init__(E_CAPACITY, f"frame overflow (bits {counts.overflow:#x}: {counts.n_pairs} pairs, "
+                                     f"{counts.n_batches} batches)")
+
+
 class Context:
     """A libhigs context: device workspace sized for the given capacities."""
 
@@ -178,19 +188,41 @@ class Context:
         if max_pairs is None:
             max_pairs = max(4 * max_gaussians, 1 << 16)
         if max_batches is None:
-            n_mt = ((max_width + 63) // 64) * ((max_height + 31) // 32)
-            max_batches = max_pairs // max(1, self.params.batch_cap) + n_mt + 16
+            max_batches = self._batches_for(max_pairs, max_width, max_height)
         self.max_gaussians, self.max_pairs, self.max_batches = int(max_gaussians), int(max_pairs), int(max_batches)
         self.max_width, self.max_height = int(max_width), int(max_height)
         self.device = device
-        h = ctypes.c_void_p()
-        _check(lib().higs_ctx_create(device, ctypes.byref(self.params), self.max_gaussians, self.max_pairs,
-                                     self.max_batches, self.max_width, self.max_height, ctypes.byref(h)),
-               "higs_ctx_create")
-        self._h = h
+        self._h = None
+        self._create()
         self.n = 0
         self.n_mt = 0
         self.frame_id = 0  # advances with every projected frame
+        self.debug_flags = 0
+        self.grown = 0  # times render_checked grew the context
+
+    def _batches_for(self, max_pairs, max_width, max_height):
+        n_mt = ((max_width + 63) // 64) * ((max_height + 31) // 32)
+        return max_pairs // max(1, self.params.batch_cap) + n_mt + 16
+
+    def _create(self):
+        h = ctypes.c_void_p()
+        _check(lib().higs_ctx_create(self.device, ctypes.byref(self.params), self.max_gaussians, self.max_pairs,
+                                     self.max_batches, self.max_width, self.max_height, ctypes.byref(h)),
+               "higs_ctx_create")
+        self._h = h
+
+    def grow(self, max_pairs: int = None, max_batches: int = None):
+        """Re-creates the device workspace with larger pair / batch
+        capacities (same gaussians, image size and parameters); the last
+        frame's intermediates are lost."""
+        mp = max(self.max_pairs, int(max_pairs or 0))
+        mb = max(self.max_batches, int(max_batches or 0), self._batches_for(mp, self.max_width, self.max_height))
+        self.close()
+        self.max_pairs, self.max_batches = mp, mb
+        self._create()
+        if self.debug_flags:
+            self.set_debug(self.debug_flags)
+        self.grown += 1
 
     def close(self):
         if getattr(self, "_h", None):
@@ -232,6 +264,24 @@ class Context:
                                  _ptr(sh), ctypes.byref(self._cam), _ptr(image), _ptr(T), _stream(stream)),
                "higs_render")
 
+    def render_checked(self, means, scales, quats, opacities, sh, cam, image, T=None, stream=None,
+                       grow: bool = True, tries: int = 4) -> "Counts":
+        """render() followed by a read of the frame's counts (synchronises).
+        On a capacity overflow the context grows to the sizes the frame asked
+        for (with 25% headroom) and renders again (grow=True), or raises
+        CapacityError (grow=False)."""
+        for _ in range(tries):
+            self.render(means, scales, quats, opacities, sh, cam, image, T, stream)
+            c = self.counts()
+            if not c.overflow:
+                return c
+            if not grow or c.overflow & ~(OVF_PAIRS | OVF_BATCHES):
+                raise CapacityError(c)
+            want_p = int(c.n_pairs * 1.25) + 1024 if c.overflow & OVF_PAIRS else self.max_pairs
+            want_b = int(c.n_batches * 1.25) + 64 if c.overflow & OVF_BATCHES else 0
+            self.grow(want_p, want_b)
+        raise CapacityError(c)
+
     def raster_backward(self, d_image, d_T, d_means, d_scales, d_quats, d_opacities, d_sh, stream=None):
         """Adjoint of the last frame (higs_raster_backward): writes the gradient
         tensors d_means [n,3], d_scales [n,3], d_quats [n,4], d_opacities [n],
@@ -248,6 +298,7 @@ class Context:
 
     def set_debug(self, flags: int):
         _check(lib().higs_set_debug(self._h, flags), "higs_set_debug")
+        self.debug_flags = int(flags)
 
     def set_timing(self, n_frames: int):
         """Keep per-kernel HIP-event times of the last n_frames frames (0: off)."""
@@ -384,13 +435,21 @@ def scene_tensors(scene, device="cuda"):
     return tuple(torch.from_numpy(np.ascontiguousarray(a)).to(device) for a in scene.arrays())
 
 
-def render(ctx: Context, tensors, cam, with_T: bool = True, stream=None):
-    """Renders one frame; returns (image [H,W,3], T [H,W] or None) device tensors."""
+def render(ctx: Context, tensors, cam, with_T: bool = True, stream=None, check: bool = True,
+           grow: bool = True):
+    """Renders one frame; returns (image [H,W,3], T [H,W] or None) device tensors.
+    check=True reads the frame's counts (a synchronisation) and, on a capacity
+    overflow, grows the context and renders again (grow=True) or raises
+    CapacityError (grow=False); check=False only enqueues the frame (an
+    overflowed frame then leaves a NaN image)."""
     import torch
     dev = tensors[0].device
     image = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device=dev)
     T = torch.empty((cam.height, cam.width), dtype=torch.float32, device=dev) if with_T else None
-    ctx.render(*tensors, cam, image, T, stream)
+    if check:
+        ctx.render_checked(*tensors, cam, image, T, stream, grow=grow)
+    else:
+        ctx.render(*tensors, cam, image, T, stream)
     return image, T
 
 
@@ -405,7 +464,9 @@ def _render_function():
         @staticmethod
         def forward(fctx, means, scales, quats, opacities, sh, hctx, cam):
             tens = tuple(t.contiguous() for t in (means, scales, quats, opacities, sh))
-            image, T = render(hctx, tens, cam)
+            # checked: a frame that overflowed its context is rendered again
+            # in a grown one, so the backward never sees a stopped frame
+            image, T = render(hctx, tens, cam, check=True)
             fctx.hctx = hctx
             fctx.frame_id = hctx.frame_id
             fctx.save_for_backward(*tens)

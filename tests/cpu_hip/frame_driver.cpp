@@ -1,0 +1,149 @@
+// Test driver for the CPU build of libhigs (see hip/hip_runtime.h): renders
+// the frames described in <in>/job.txt through the library's C-ABI and writes
+// what the tests compare (counts, image, transmittance, sorted pairs, batch
+// table) into <out>.
+//
+// job.txt: one frame per line after a header line "n max_pairs max_batches
+// sort_mode batch_cap n_cus entry" (entry 0 = higs_render on a context, 1 = the
+// allocation-free entry point); a frame line is "n_use W H fx fy cx cy
+// R00 .. t2 (12 floats) bg0 bg1 bg2".  Scene arrays are raw float32 files
+// means, scales, quats, opac, sh in <in>.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/higs.h"
+
+static std::vector<float> load(const std::string& path, size_t count) {
+  std::vector<float> v(count);
+  FILE* f = fopen(path.c_str(), "rb");
+  if (!f || fread(v.data(), 4, count, f) != count) {
+    fprintf(stderr, "cannot read %s\n", path.c_str());
+    exit(2);
+  }
+  fclose(f);
+  return v;
+}
+
+static void save(const std::string& path, const void* p, size_t bytes) {
+  FILE* f = fopen(path.c_str(), "wb");
+  if (!f || (bytes && fwrite(p, 1, bytes, f) != bytes)) {
+    fprintf(stderr, "cannot write %s\n", path.c_str());
+    exit(2);
+  }
+  fclose(f);
+}
+
+extern "C" int higs_render_noalloc(int64_t n, const float* means, const float* scales,
+                                   const float* quats, const float* opacities, const float* sh,
+                                   const higs_camera* cam, float* image, float* T_out,
+                                   void* stream) __attribute__((weak));
+
+int main(int argc, char** argv) {
+  if (argc != 3) {
+    fprintf(stderr, "usage: frame_driver <in> <out>\n");
+    return 2;
+  }
+  const std::string in = argv[1], out = argv[2];
+  FILE* jf = fopen((in + "/job.txt").c_str(), "r");
+  if (!jf) return 2;
+  long long n, max_pairs, max_batches;
+  int sort_mode, batch_cap, n_cus, entry;
+  if (fscanf(jf, "%lld %lld %lld %d %d %d %d", &n, &max_pairs, &max_batches, &sort_mode,
+             &batch_cap, &n_cus, &entry) != 7)
+    return 2;
+  std::vector<float> means = load(in + "/means", (size_t)n * 3);
+  std::vector<float> scales = load(in + "/scales", (size_t)n * 3);
+  std::vector<float> quats = load(in + "/quats", (size_t)n * 4);
+  std::vector<float> opac = load(in + "/opac", (size_t)n);
+  std::vector<float> sh = load(in + "/sh", (size_t)n * 48);
+  higs_params p;
+  higs_default_params(&p);
+  p.sort_mode = sort_mode;
+  p.batch_cap = batch_cap;
+  higs_ctx* ctx = nullptr;
+  int max_w = 1, max_h = 1;
+  std::vector<higs_camera> cams;
+  std::vector<long long> uses;
+  for (;;) {
+    higs_camera c;
+    long long use;
+    if (fscanf(jf, "%lld %d %d %f %f %f %f", &use, &c.width, &c.height, &c.fx, &c.fy, &c.cx,
+               &c.cy) != 7)
+      break;
+    for (int k = 0; k < 12; ++k)
+      if (fscanf(jf, "%f", &c.world_to_cam[k]) != 1) return 2;
+    for (int k = 0; k < 3; ++k)
+      if (fscanf(jf, "%f", &c.background[k]) != 1) return 2;
+    cams.push_back(c);
+    uses.push_back(use);
+    if (c.width > max_w) max_w = c.width;
+    if (c.height > max_h) max_h = c.height;
+  }
+  fclose(jf);
+  const int debug_flags = getenv("HIGS_CPU_DEBUG") ? atoi(getenv("HIGS_CPU_DEBUG")) : 0;
+  if (entry == 0) {
+    const int rc = higs_ctx_create(0, &p, n, max_pairs, max_batches, max_w, max_h, &ctx);
+    if (rc) {
+      fprintf(stderr, "higs_ctx_create: %d\n", rc);
+      return 3;
+    }
+    if (debug_flags && higs_set_debug(ctx, debug_flags)) return 3;
+  }
+  FILE* summary = fopen((out + "/counts.txt").c_str(), "w");
+  for (size_t f = 0; f < cams.size(); ++f) {
+    const higs_camera& c = cams[f];
+    const size_t npx = (size_t)c.width * c.height;
+    std::vector<float> image(npx * 3, -7.0f), T(npx, -7.0f);
+    int rc = 0;
+    higs_counts cn{};
+    const std::string pre = out + "/f" + std::to_string(f) + "_";
+    if (entry == 0) {
+      // stage by stage, reading back each stage's output as soon as it exists,
+      // so that a failure names its stage
+      rc = higs_project(ctx, uses[f], means.data(), scales.data(), quats.data(), opac.data(),
+                        sh.data(), &c, nullptr);
+      if (!rc) rc = higs_bin_sort(ctx, nullptr);
+      if (!rc && higs_get_counts(ctx, &cn)) return 4;
+      if (!rc && !cn.overflow && (debug_flags & HIGS_DEBUG_KEEP_PAIRS)) {
+        const size_t np = (size_t)cn.n_pairs;
+        std::vector<unsigned char> pairs(np * 12);
+        if (np && higs_debug_copy(ctx, HIGS_DBG_PAIRS, pairs.data(), pairs.size())) return 4;
+        save(pre + "pairs", pairs.data(), pairs.size());
+      }
+      if (!rc && !cn.overflow) {
+        const size_t np = (size_t)cn.n_pairs;
+        std::vector<unsigned char> pairs(np * 12);
+        if (np && higs_debug_copy(ctx, HIGS_DBG_SORTED, pairs.data(), pairs.size())) return 4;
+        save(pre + "sorted", pairs.data(), pairs.size());
+      }
+      if (!rc) rc = higs_batch(ctx, nullptr);
+      if (!rc && higs_get_counts(ctx, &cn)) return 4;
+      if (!rc && !cn.overflow) {
+        const size_t nb = (size_t)cn.n_batches;
+        std::vector<uint32_t> tab(nb * 3);
+        if (nb && higs_debug_copy(ctx, HIGS_DBG_BATCHES, tab.data(), tab.size() * 4)) return 4;
+        save(pre + "batches", tab.data(), tab.size() * 4);
+      }
+      if (!rc) rc = higs_raster(ctx, image.data(), T.data(), nullptr);
+      if (!rc && higs_get_counts(ctx, &cn)) return 4;
+    } else {
+      rc = higs_render_noalloc ? higs_render_noalloc(uses[f], means.data(), scales.data(),
+                                                     quats.data(), opac.data(), sh.data(), &c,
+                                                     image.data(), T.data(), nullptr)
+                               : -100;
+    }
+    save(pre + "image", image.data(), image.size() * 4);
+    save(pre + "T", T.data(), T.size() * 4);
+    fprintf(summary, "%d %lld %lld %lld %lld %u\n", rc, (long long)cn.n_visible,
+            (long long)cn.n_pairs, (long long)cn.n_batches, (long long)cn.n_evaluations,
+            cn.overflow);
+    fflush(summary);
+  }
+  fclose(summary);
+  if (ctx) higs_ctx_destroy(ctx);
+  return 0;
+}

@@ -72,37 +72,47 @@ def test_stage_order_and_capacity_errors():
 
 
 @pytest.mark.gpu
-@pytest.mark.skip(reason="kept off the GPU: with an experimental cross-batch saturation skip in "
-                  "the rasteriser this case went silent on the GPU twice and the cause was not "
-                  "found; that rasteriser is removed, the case passes in a CPU build, and it "
-                  "returns to the GPU once the cause is shown")
 def test_pair_overflow_is_reported_then_retry_succeeds(orc):
+    """The overflow protocol (the same capacities run in the CPU build of the
+    library under AddressSanitizer, tests/test_cpu_build.py): a frame that
+    needs more pairs or batches than its context holds stops on the device
+    (NaN image and T), the counts report the sizes it needed, and a context of
+    those sizes renders the oracle's image."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    print("overflow case: config0 view 0, 16 pairs / 4 batches", flush=True)
     sc, cams = scenes.config0()
     cam = cams[0]
     t = higs.scene_tensors(sc)
     ctx = higs.Context(sc.n, 256, 256, max_pairs=16, max_batches=4)
-    img, T = higs.render(ctx, t, cam)
+    img, T = higs.render(ctx, t, cam, check=False)
     torch.cuda.synchronize()
     c = ctx.counts()
-    assert c.overflow & higs.OVF_PAIRS
-    assert c.n_pairs > 16
-    # grow from the reported sizes and render again
-    ctx2 = higs.Context(sc.n, 256, 256, max_pairs=int(c.n_pairs), max_batches=int(c.n_pairs))
-    img, T = higs.render(ctx2, t, cam)
+    assert c.overflow == higs.OVF_PAIRS
+    assert c.n_pairs > 16 and c.n_batches == 0
+    assert torch.isnan(img).all() and torch.isnan(T).all()
+    with pytest.raises(higs.CapacityError):
+        higs.render(ctx, t, cam, grow=False)
+    # batch-table overflow alone
+    ctx2 = higs.Context(sc.n, 256, 256, max_pairs=int(c.n_pairs), max_batches=3)
+    img2, _ = higs.render(ctx2, t, cam, check=False)
     torch.cuda.synchronize()
     c2 = ctx2.counts()
-    assert c2.overflow == 0 and c2.n_pairs == c.n_pairs
-    fr = orc.frame(sc, cam)
-    d = np.abs(img.cpu().numpy() - fr.image)[fr.amb == 0]
-    assert d.max() <= 2e-4
-    # batch-table overflow alone
-    ctx3 = higs.Context(sc.n, 256, 256, max_pairs=int(c.n_pairs), max_batches=3)
-    higs.render(ctx3, t, cam)
+    assert c2.overflow == higs.OVF_BATCHES and c2.n_batches > 3
+    assert torch.isnan(img2).all()
+    # exactly the reported sizes
+    ctx3 = higs.Context(sc.n, 256, 256, max_pairs=int(c.n_pairs), max_batches=int(c2.n_batches))
+    img3, _ = higs.render(ctx3, t, cam, check=False)
     torch.cuda.synchronize()
-    assert ctx3.counts().overflow == higs.OVF_BATCHES
+    assert ctx3.counts().overflow == 0
+    fr = orc.frame(sc, cam)
+    d = np.abs(img3.cpu().numpy().astype(np.float64) - fr.image)
+    assert d[fr.amb == 0].max() <= 2e-4 and d.mean() <= 1e-5
+    # the checked render grows the first context and renders again
+    img4, _ = higs.render(ctx, t, cam)
+    assert ctx.grown >= 1 and ctx.counts().overflow == 0
+    assert torch.equal(img4, img3)
 
 
 def test_struct_layouts_match_the_header(tmp_path):

@@ -1,0 +1,60 @@
+"""The library's own HIP sources, built for the host against the CPU stand-in
+runtime (tests/cpu_hip/: work-items as threads, AddressSanitizer on every
+access), run through the C-ABI on small frames.  These tests need no GPU:
+they check that every kernel terminates and stays inside its buffers, at
+capacities the GPU tests use too, and compare the frames with the oracle."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2606_00352_amd import scenes
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _cpu():
+    sys.path.insert(0, os.path.join(HERE, "cpu_hip"))
+    import cpu_build
+    if not cpu_build.available():
+        pytest.skip("no host clang++")
+    return cpu_build
+
+
+def test_small_frame_matches_the_oracle(orc):
+    """Pairs, sort order and batches bit-exact, image within the tolerance."""
+    cpu = _cpu()
+    scene = scenes.uniform_scene(3000, seed=7)
+    cam = scenes.camera_at_origin(160, 96, 140.0, (0.1, 0.2, 0.3))
+    fr = cpu.run_frames(scene, [cam], max_pairs=1 << 16, max_batches=4096)[0]
+    o = orc.frame(scene, cam)
+    assert fr.rc == 0 and fr.overflow == 0
+    want = (o.sorted_mt.astype(np.uint64) << np.uint64(32)) | o.sorted_key.astype(np.uint64)
+    assert np.array_equal(fr.keys, want)
+    assert np.array_equal(fr.ids, o.sorted_gid.astype(np.uint32))
+    assert np.array_equal(fr.batches.astype(np.int64), o.batch_tab.astype(np.int64))
+    d = np.abs(fr.image.astype(np.float64) - o.image)
+    assert d[o.amb == 0].max() <= 2e-4 and d.mean() <= 1e-5
+
+
+def test_capacity_overflow_stops_the_frame(orc):
+    """The overflow protocol at the GPU test's capacities (16 pairs, 4
+    batches): every stage after the pair scan returns at once, the image and
+    T are NaN, the counts report what the frame needed; a context of exactly
+    those sizes renders the oracle's image."""
+    cpu = _cpu()
+    sc, cams = scenes.config0()
+    cam = cams[0]
+    fr = cpu.run_frames(sc, [cam], max_pairs=16, max_batches=4)[0]
+    assert fr.rc == 0 and fr.overflow == 1          # pairs only: the batch stage never ran
+    assert fr.n_pairs > 16 and fr.n_batches == 0
+    assert np.isnan(fr.image).all() and np.isnan(fr.T).all()
+    fb = cpu.run_frames(sc, [cam], max_pairs=fr.n_pairs, max_batches=3)[0]
+    assert fb.overflow == 2 and fb.n_pairs == fr.n_pairs and fb.n_batches > 3
+    assert np.isnan(fb.image).all()
+    ok = cpu.run_frames(sc, [cam], max_pairs=fr.n_pairs, max_batches=fb.n_batches)[0]
+    assert ok.overflow == 0
+    o = orc.frame(sc, cam)
+    d = np.abs(ok.image.astype(np.float64) - o.image)
+    assert d[o.amb == 0].max() <= 2e-4 and d.mean() <= 1e-5
