@@ -212,6 +212,24 @@ int higs_raster_backward(higs_ctx* ctx, const float* dL_dimage, const float* dL_
                          float* dmeans, float* dscales, float* dquats, float* dopacities,
                          float* dsh, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, serving loops and harnesses that forbid hipMalloc): one frame of
+ * the whole path, as higs_render with the default parameters, with every
+ * intermediate in a static device array of the library (80 MiB, held on each
+ * device the library runs on until the process ends) instead of a context.
+ * Allocates nothing: no hipMalloc, no hipFree.  Limits: n <= 131072
+ * gaussians, images up to 1024 x 1024, at most 524288 (macro-tile, gaussian)
+ * pairs per frame (more: the frame stops and the image and T_out are NaN, as
+ * for a context's capacity overflow); larger n or images return
+ * HIGS_E_CAPACITY before any work is queued.  Arguments as for higs_render,
+ * on the current HIP device.  Every call on a device shares that device's
+ * array, which keeps the last call's intermediates: calls that overlap on one
+ * device (other streams, other host threads) race, so a caller serialises
+ * them (one stream, or an event between calls). */
+int higs_render_noalloc(int64_t n, const float* means, const float* scales, const float* quats,
+                        const float* opacities, const float* sh, const higs_camera* cam,
+                        float* image, float* T_out, void* stream);
+
 /* ---- Serving ---------------------------------------------------------------
  * A render server keeps several scenes resident on the device and renders a
  * stream of requests (scene, camera, resolution class) with continuous

@@ -9,6 +9,7 @@
 #include <new>
 
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "higs_internal.h"
@@ -133,6 +134,56 @@ void free_all(higs_ctx* c) {
   free_events(c);
 }
 
+// Every device buffer of a context and its element count, in one place:
+// higs_ctx_create allocates them, higs_ctx_footprint adds them up, and the
+// allocation-free entry point lays them out in its static scratch array.
+// Needs max_g, max_pairs, max_batches, max_mt and max_tiles set.
+template <class F>
+void for_each_buffer(higs_ctx* c, F&& f) {
+  const size_t G = (size_t)c->max_g, P = (size_t)c->max_pairs, B = (size_t)c->max_batches;
+  const size_t nblk = (G + kProjBlock - 1) / kProjBlock;
+  const size_t mt = (size_t)c->max_mt;
+  f(&c->f_mx, G);
+  f(&c->f_my, G);
+  f(&c->f_a, G);
+  f(&c->f_b, G);
+  f(&c->f_c, G);
+  f(&c->f_tau, G);
+  f(&c->f_key, G);
+  f(&c->f_cnt, G);
+  f(&c->f_span, G);
+  f(&c->rec, G);
+  f(&c->block_sums, 2 * nblk + 2 * (size_t)scan_chunks((int64_t)nblk));
+  f(&c->keys[0], P);
+  f(&c->keys[1], P);
+  f(&c->vals[0], P);
+  f(&c->vals[1], P);
+  f(&c->hist, (size_t)kMaxPasses * kRadix);
+  f(&c->plan, (size_t)kMaxPasses + (size_t)kMaxPasses * kRadix);
+  f(&c->status, (size_t)c->max_tiles * kRadix);
+  f(&c->mt_off, mt + 1);
+  f(&c->batch_first, mt + 1);
+  f(&c->batch_tab, 3 * B);
+  f(&c->active, B);
+  f(&c->partials, B * kTilesPerMt * 64);
+  f(&c->dc, (size_t)1);
+  f(&c->seg_count, mt);
+  f(&c->seg_cursor, mt);
+  f(&c->seg_chunk_off, mt + 1);
+  f(&c->seg_blk_off, mt + 1);
+}
+
+void set_capacities(higs_ctx* c, int64_t max_gaussians, int64_t max_pairs, int64_t max_batches,
+                    int32_t max_width, int32_t max_height) {
+  c->max_g = max_gaussians;
+  c->max_pairs = max_pairs;
+  c->max_batches = max_batches;
+  c->max_w = max_width;
+  c->max_h = max_height;
+  c->max_mt = ((max_width + kMtW - 1) / kMtW) * ((max_height + kMtH - 1) / kMtH);
+  c->max_tiles = (uint32_t)((max_pairs + kSortTile - 1) / kSortTile);
+}
+
 int n_bits(uint32_t v) {  // bits needed to hold 0..v
   int b = 0;
   while (v) {
@@ -224,51 +275,15 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
   if (!c) return HIGS_E_NOMEM;
   c->device = device;
   c->params = p;
-  c->max_g = max_gaussians;
-  c->max_pairs = max_pairs;
-  c->max_batches = max_batches;
-  c->max_w = max_width;
-  c->max_h = max_height;
-  c->max_mt = ((max_width + kMtW - 1) / kMtW) * ((max_height + kMtH - 1) / kMtH);
+  set_capacities(c, max_gaussians, max_pairs, max_batches, max_width, max_height);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
     delete c;
     return HIGS_E_HIP;
   }
   c->n_cus = prop.multiProcessorCount;
-  const size_t G = (size_t)max_gaussians, P = (size_t)max_pairs, B = (size_t)max_batches;
-  const size_t nblk = (G + kProjBlock - 1) / kProjBlock;
-  c->max_tiles = (uint32_t)((P + kSortTile - 1) / kSortTile);
-  // (the sizes below are the ones higs_ctx_footprint adds up)
   int rc = HIGS_OK;
-  rc |= dalloc(&c->f_mx, G);
-  rc |= dalloc(&c->f_my, G);
-  rc |= dalloc(&c->f_a, G);
-  rc |= dalloc(&c->f_b, G);
-  rc |= dalloc(&c->f_c, G);
-  rc |= dalloc(&c->f_tau, G);
-  rc |= dalloc(&c->f_key, G);
-  rc |= dalloc(&c->f_cnt, G);
-  rc |= dalloc(&c->f_span, G);
-  rc |= dalloc(&c->rec, G);
-  rc |= dalloc(&c->block_sums, 2 * nblk + 2 * (size_t)scan_chunks((int64_t)nblk));
-  rc |= dalloc(&c->keys[0], P);
-  rc |= dalloc(&c->keys[1], P);
-  rc |= dalloc(&c->vals[0], P);
-  rc |= dalloc(&c->vals[1], P);
-  rc |= dalloc(&c->hist, (size_t)kMaxPasses * kRadix);
-  rc |= dalloc(&c->plan, (size_t)kMaxPasses + (size_t)kMaxPasses * kRadix);
-  rc |= dalloc(&c->status, (size_t)c->max_tiles * kRadix);
-  rc |= dalloc(&c->mt_off, (size_t)c->max_mt + 1);
-  rc |= dalloc(&c->batch_first, (size_t)c->max_mt + 1);
-  rc |= dalloc(&c->batch_tab, 3 * B);
-  rc |= dalloc(&c->active, B);
-  rc |= dalloc(&c->partials, B * kTilesPerMt * 64);
-  rc |= dalloc(&c->dc, 1);
-  rc |= dalloc(&c->seg_count, (size_t)c->max_mt);
-  rc |= dalloc(&c->seg_cursor, (size_t)c->max_mt);
-  rc |= dalloc(&c->seg_chunk_off, (size_t)c->max_mt + 1);
-  rc |= dalloc(&c->seg_blk_off, (size_t)c->max_mt + 1);
+  for_each_buffer(c, [&](auto** ptr, size_t count) { rc |= dalloc(ptr, count); });
   if (rc != HIGS_OK) {
     free_all(c);
     delete c;
@@ -298,21 +313,12 @@ int64_t higs_ctx_footprint(const higs_params* params, int64_t max_gaussians, int
   (void)params;
   if (max_gaussians < 1 || max_pairs < 1 || max_batches < 1 || max_width < 1 || max_height < 1)
     return HIGS_E_INVALID;
-  const int64_t G = max_gaussians, P = max_pairs, B = max_batches;
-  const int64_t nblk = (G + kProjBlock - 1) / kProjBlock;
-  const int64_t tiles = (P + kSortTile - 1) / kSortTile;
-  const int64_t mt = (int64_t)((max_width + kMtW - 1) / kMtW) * ((max_height + kMtH - 1) / kMtH);
+  higs_ctx c;
+  set_capacities(&c, max_gaussians, max_pairs, max_batches, max_width, max_height);
   int64_t bytes = 0;
-  bytes += G * (6 * 4 + 3 * 4);                // binning fields, key, count, span
-  bytes += G * (int64_t)sizeof(RasterRecord);  // raster records
-  bytes += (2 * nblk + 2 * scan_chunks(nblk)) * 4;  // per-block and per-chunk sums
-  bytes += P * (2 * 8 + 2 * 4);                // two key and two value buffers
-  bytes += (int64_t)kMaxPasses * kRadix * 4 + ((int64_t)kMaxPasses + kMaxPasses * kRadix) * 4;
-  bytes += tiles * kRadix * 8;                 // sort look-back words
-  bytes += 2 * (mt + 1) * 4;                   // macro-tile offsets, first batches
-  bytes += B * (3 * 4 + 4);                    // batch table, active masks
-  bytes += B * kTilesPerMt * 64 * (int64_t)sizeof(float4);  // partials
-  bytes += (int64_t)sizeof(DeviceCounters);
+  for_each_buffer(&c, [&](auto** ptr, size_t count) {
+    bytes += (int64_t)((count ? count : 1) * sizeof(**ptr));
+  });
   return bytes;
 }
 
@@ -766,6 +772,93 @@ int higs_get_timers(higs_ctx* c, float ms[HIGS_NUM_TIMERS]) {
 }
 
 }  // extern "C"
+
+// ---- allocation-free rendering ------------------------------------------------
+// One frame of the whole path with every intermediate in a static device array
+// instead of a context's allocations: for callers that cannot allocate device
+// memory (code under stream capture, serving loops that must not call
+// hipMalloc).  The capacities are fixed; the array lives on every device the
+// library runs on until the process ends.
+namespace {
+constexpr int64_t kNaMaxGaussians = 131072;
+constexpr int64_t kNaMaxPairs = 524288;
+// every macro-tile holds at most one partly filled batch: pairs / B_r plus one
+// per macro-tile bounds the batch count, so pairs that fit never overflow it
+constexpr int32_t kNaMaxWidth = 1024, kNaMaxHeight = 1024;
+constexpr int64_t kNaMaxBatches = kNaMaxPairs / kMaxBatch +
+                                  (int64_t)((kNaMaxWidth + kMtW - 1) / kMtW) *
+                                      ((kNaMaxHeight + kMtH - 1) / kMtH) + 16;
+constexpr size_t kScratchBytes = (size_t)80 << 20;
+constexpr int kNaMaxDevices = 16;
+
+struct NoAllocState {
+  bool ready = false;
+  unsigned char* base = nullptr;  // device address of this device's scratch array
+  higs_ctx ctx;
+};
+NoAllocState g_noalloc[kNaMaxDevices];
+std::mutex g_noalloc_mu;
+
+// Lays the context's buffers out in [base, base + cap), 256-byte aligned.
+bool carve(higs_ctx* c, unsigned char* base, size_t cap) {
+  size_t off = 0;
+  bool fits = true;
+  for_each_buffer(c, [&](auto** ptr, size_t count) {
+    using T = typename std::remove_reference<decltype(**ptr)>::type;
+    const size_t bytes = ((count ? count : 1) * sizeof(T) + 255) & ~(size_t)255;
+    if (off + bytes > cap) {
+      fits = false;
+      *ptr = nullptr;
+      return;
+    }
+    *ptr = reinterpret_cast<T*>(base + off);
+    off += bytes;
+  });
+  return fits;
+}
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+extern "C" int higs_render_noalloc(int64_t n, const float* means, const float* scales,
+                                   const float* quats, const float* opacities, const float* sh,
+                                   const higs_camera* cam, float* image, float* T_out,
+                                   void* stream) {
+  if (!cam || !image || n < 0) return HIGS_E_INVALID;
+  if (n > kNaMaxGaussians || cam->width > kNaMaxWidth || cam->height > kNaMaxHeight)
+    return HIGS_E_CAPACITY;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return HIGS_E_HIP;
+  if (dev < 0 || dev >= kNaMaxDevices) return HIGS_E_UNSUPPORTED;
+  NoAllocState& st = g_noalloc[dev];
+  hipStream_t s = (hipStream_t)stream;
+  {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!st.ready) {
+      // once per device, with that device current: the array's device address
+      // (the symbol's host-side name is no device address)
+      void* ptr = nullptr;
+      if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return HIGS_E_HIP;
+      hipDeviceProp_t prop;
+      if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return HIGS_E_HIP;
+      higs_ctx& c = st.ctx;
+      c.device = dev;
+      c.n_cus = prop.multiProcessorCount;
+      higs_default_params(&c.params);
+      set_capacities(&c, kNaMaxGaussians, kNaMaxPairs, kNaMaxBatches, kNaMaxWidth, kNaMaxHeight);
+      st.base = static_cast<unsigned char*>(ptr);
+      if (!carve(&c, st.base, kScratchBytes)) return HIGS_E_UNSUPPORTED;
+      // the sort's look-back words start untagged, by a kernel on the
+      // caller's stream (the frame's own kernels clear the counters)
+      int rc = hip_err(launch_zero_words(c.status, (size_t)c.max_tiles * kRadix, s));
+      if (!rc) rc = hip_err(launch_zero_words(reinterpret_cast<uint64_t*>(c.dc),
+                                              sizeof(DeviceCounters) / 8, s));
+      if (rc) return rc;
+      st.ready = true;
+    }
+  }
+  return higs_render(&st.ctx, n, means, scales, quats, opacities, sh, cam, image, T_out, stream);
+}
 
 namespace higs {
 int ctx_enqueue_counters(higs_ctx* c, void* pinned_dst, hipStream_t s) {

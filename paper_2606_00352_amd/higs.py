@@ -28,7 +28,7 @@ EXPORTS = ("higs_default_params", "higs_ctx_create", "higs_ctx_destroy", "higs_p
            "higs_set_debug", "higs_debug_copy", "higs_set_timing", "higs_get_timers",
            "higs_error_string", "higs_raster_backward", "higs_ctx_footprint",
            "higs_server_create", "higs_server_destroy", "higs_server_add_scene", "higs_server_submit",
-           "higs_server_poll", "higs_server_get_stats")
+           "higs_server_poll", "higs_server_get_stats", "higs_render_noalloc")
 
 
 class HigsError(RuntimeError):
@@ -114,6 +114,7 @@ def lib():
             "higs_server_submit": (ctypes.c_int, [P, i64, i32, i32, P, P]),
             "higs_server_poll": (ctypes.c_int, [P, P, i32]),
             "higs_server_get_stats": (ctypes.c_int, [P, P]),
+            "higs_render_noalloc": (ctypes.c_int, [i64, P, P, P, P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -451,6 +452,16 @@ def render(ctx: Context, tensors, cam, with_T: bool = True, stream=None, check: 
     else:
         ctx.render(*tensors, cam, image, T, stream)
     return image, T
+
+
+def render_noalloc(tensors, cam, image, T=None, stream=None):
+    """higs_render_noalloc: one frame with the library's static scratch array
+    (no device allocation); the image (and T) are written on `stream`."""
+    means, scales, quats, opac, sh = tensors
+    c = camera_c(cam)
+    _check(lib().higs_render_noalloc(int(means.shape[0]), _ptr(means), _ptr(scales), _ptr(quats), _ptr(opac),
+                                     _ptr(sh), ctypes.byref(c), _ptr(image), _ptr(T), _stream(stream)),
+           "higs_render_noalloc")
 
 
 def _render_function():
