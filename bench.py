@@ -58,14 +58,14 @@ COPY_CALIBRATION_BYTES = 1 << 30
 MEASURED_TRAFFIC = {
     # profiles/frame_1080p_5p8m_hbm_traffic.md (sort: histogram + plan + every
     # onesweep dispatch of a frame)
-    "raster": {"src_sha256": "c42e8ca2c82cd95d583602cc54b7912add76e0d1e09ed2b6f1682a42dedf48e1",
-              "bytes_per_launch": 1514590900},
-    "project": {"src_sha256": "db411b7566132f710396085286974f14bb354333c462ac24df2ee3478df62007",
-               "bytes_per_launch": 1714748482},
-    "fill": {"src_sha256": "1c2814b893dce0127c74d3691e143e1f611fb9c5075ccd12dba20e87f9014ce2",
-            "bytes_per_launch": 134934784},
-    "sort": {"src_sha256": "14e183273f7893df42277b8c779a1dd4212cbfc9bd491af5b974391978123fc5",
-            "bytes_per_launch": 909053082},
+    "raster": {"src_sha256": "724d956896ea5bb85d9e407b44a58382ceccde693cd192802fa38f80c997697c",
+              "bytes_per_launch": 1512400000},
+    "project": {"src_sha256": "48cfee213d0d1466f6388dd8aaa1b31ebdd0dff844796802d96498c54dad2bfa",
+               "bytes_per_launch": 1714600000},
+    "fill": {"src_sha256": "95c563041c3f244863417a23f709a99ab5ff86b18ffad3b356695d4ca31938b8",
+            "bytes_per_launch": 134900000},
+    "sort": {"src_sha256": "d19c0c33859fee1d5b0994afbaa4403bf3e924b751f6fce897d7cdd051e942df",
+            "bytes_per_launch": 914500000},
 }
 # the sources each figure depends on (the shared header holds the kernels' shapes)
 KERNEL_SOURCES = {"project": ("project.hip", "predicate.h", "higs_internal.h"),
@@ -329,6 +329,57 @@ def protocol_median(ctx, tens, cams, image, iters=10):
     return float(np.median(ms)), per_view
 
 
+def leg_reduced(scene, tens, cams, steps=120, warmup=10):
+    """The reduced-precision mode on the main workload: the half-precision
+    raster, alone and with the 32-byte packed SH, timed like the main loop;
+    PSNR of each against the float32 frame, mean over orbit views 0, 10, ..., 50."""
+    import numpy as np
+    import torch
+    from paper_2606_00352_amd import higs
+    out = {}
+    ref_ctx = higs.Context(scene.n, 1920, 1080, max_pairs=3 * scene.n)
+    image = torch.empty((1080, 1920, 3), dtype=torch.float32, device="cuda:0")
+    refs = {}
+    for v in CPU_VIEWS:
+        ref_ctx.render_checked(*tens, cams[v], image)
+        refs[v] = image.double().clone()
+    ref_ctx.close()
+    t0 = time.perf_counter()
+    packed = higs.sh_compress(tens[4], tens[3])
+    torch.cuda.synchronize()
+    compress_s = time.perf_counter() - t0
+    for name, params, sh in (("fp16_raster", {"raster_precision": higs.RASTER_FP16}, tens[4]),
+                             ("fp16_raster_packed_sh", {"raster_precision": higs.RASTER_FP16,
+                                                        "sh_format": higs.SH_PACKED32}, packed),
+                             ("packed_sh", {"sh_format": higs.SH_PACKED32}, packed)):
+        t = (*tens[:4], sh)
+        ctx = higs.Context(scene.n, 1920, 1080, max_pairs=3 * scene.n, **params)
+        psnr = []
+        for v in CPU_VIEWS:
+            ctx.render_checked(*t, cams[v], image)
+            mse = float(torch.mean((image.double() - refs[v]) ** 2))
+            psnr.append(10.0 * np.log10(1.0 / mse) if mse > 0 else float("inf"))
+        for i in range(warmup):
+            ctx.render(*t, cams[i % len(cams)], image)
+        torch.cuda.synchronize()
+        ctx.set_timing(min(steps, 1024))
+        t0 = time.perf_counter()
+        for i in range(steps):
+            ctx.render(*t, cams[i % len(cams)], image)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        timers = ctx.timers()
+        assert ctx.counts().overflow == 0
+        out[name] = {"fps": round(1.0 / dt, 2), "ms_per_frame": round(dt * 1e3, 4),
+                     "psnr_db_vs_fp32_mean": round(float(np.mean(psnr)), 2),
+                     "psnr_db_vs_fp32_min": round(float(np.min(psnr)), 2),
+                     "kernel_ms": {k: round(v, 4) for k, v in timers.items()}}
+        ctx.close()
+    out["sh_compress_s"] = round(compress_s, 3)
+    out["workload"] = "the main workload; PSNR over orbit views 0, 10, ..., 50 (peak 1.0)"
+    return out
+
+
 def leg_4k(warmup=10, steps=60):
     """FPS on the 4K workload (6M clustered gaussians, 3840x2160, f = 2200,
     60-view orbit): one frame per view, timed like the main loop."""
@@ -366,6 +417,9 @@ def main():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-4k", action="store_true")
+    ap.add_argument("--no-reduced", action="store_true")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only the warm-up and the timed frames (for rocprofv3 runs)")
     ap.add_argument("--protocol-iters", type=int, default=10,
                     help="frames per view of the per-frame median (the paper times 100)")
     ap.add_argument("--sort", choices=("onesweep", "segmented"), default="onesweep",
@@ -429,6 +483,10 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     timers = ctx.timers()
     ctx.set_timing(0)
+    if args.profile_run:
+        print(json.dumps({"profile_run": True, "steps": args.steps, "ms_per_step": round(ms_per_step, 4),
+                          "kernel_ms": {k: round(v, 4) for k, v in timers.items()}}), flush=True)
+        return
     log("kernel ms: " + ", ".join(f"{k} {v:.4f}" for k, v in timers.items()))
 
     # sizes per view (outside the timed region), evaluation count by the
@@ -515,6 +573,11 @@ def main():
                      "unit": unit, "frac": round(ach / peak, 4),
                      "traffic": measured_traffic(traffic_key(dom, seg))},
     }
+    if not args.no_reduced:
+        log("reduced-precision leg")
+        ctx.close()
+        result["reduced_precision"] = leg_reduced(scene, tens, cams)
+        log(f"reduced precision: {result['reduced_precision']}")
     if not args.no_4k:
         log("4K leg")
         del ctx

@@ -89,7 +89,25 @@ typedef struct {
   float near_z;       /* cull at camera-space depth <= near_z (0.2) */
   float dilation;     /* added to the 2D covariance diagonal (0.3) */
   int32_t sort_mode;  /* HIGS_SORT_ONESWEEP (default) or HIGS_SORT_SEGMENTED */
+  int32_t raster_precision; /* HIGS_RASTER_FP32 (default) or HIGS_RASTER_FP16 */
+  int32_t sh_format;  /* HIGS_SH_FLOAT32 (default) or HIGS_SH_PACKED32 */
 } higs_params;
+
+/* Reduced-precision mode (sec. 3.5 "Numerical representation" and sec. 4.5
+ * "Numerical format"): HIGS_RASTER_FP16 rasterises in packed half precision
+ * (prescaled Cholesky factors, coordinates relative to the macro-tile centre,
+ * two pixels per lane, 8-byte partials) and checks the transmittance cut-off
+ * once per 64 gaussians instead of per gaussian.  Projection, pairs, sort
+ * order and batches are the float32 mode's, bit for bit; the image is not held
+ * to the float32 tolerance (the paper judges this mode by PSNR against the
+ * float32 renderer).  higs_raster_backward is not available in this mode. */
+#define HIGS_RASTER_FP32 0
+#define HIGS_RASTER_FP16 1
+/* SH input of higs_project: HIGS_SH_FLOAT32 = float [n, (deg+1)^2, 3];
+ * HIGS_SH_PACKED32 = the 32-byte representation of sec. 4.2 written by
+ * higs_sh_compress (degree 3 only). */
+#define HIGS_SH_FLOAT32 0
+#define HIGS_SH_PACKED32 1
 
 /* How pairs are binned and depth-ordered; both give the same (macro-tile,
  * depth, id) order.  SEGMENTED: binning straight into per-macro-tile segments
@@ -211,6 +229,23 @@ int higs_render(higs_ctx* ctx, int64_t n, const float* means, const float* scale
 int higs_raster_backward(higs_ctx* ctx, const float* dL_dimage, const float* dL_dT,
                          float* dmeans, float* dscales, float* dquats, float* dopacities,
                          float* dsh, void* stream);
+
+/* Packed SH (sec. 4.2, the 32-byte SH representation): the colour
+ * coefficients of every gaussian go to YCoCg (luma, two chroma differences),
+ * are scaled per basis and component by a high percentile (99.9%) of their
+ * magnitude over the gaussians with opacity >= 1/255, pass through a
+ * square-root gamma and are quantised to 6 bits of luma and 4 of chroma (the
+ * DC basis to 12 and 10 bits), 32 bytes per gaussian after a 256-byte header
+ * of 48 float32 scales.  higs_sh_packed_bytes(n) is the size of that buffer.
+ * higs_sh_compress writes it from sh [n, 16, 3] and opacities [n] (device)
+ * into `packed` (device, 16-byte aligned, higs_sh_packed_bytes(n) bytes,
+ * caller-owned); it runs on the current device, allocates a 196 KiB work area
+ * and synchronises the stream before returning.  A context created with
+ * sh_format = HIGS_SH_PACKED32 then takes `packed` as the sh argument of
+ * higs_project. */
+int64_t higs_sh_packed_bytes(int64_t n);
+int higs_sh_compress(int64_t n, const float* sh, const float* opacities, void* packed,
+                     void* stream);
 
 /* For callers that cannot allocate device memory (code under HIP stream
  * capture, serving loops and harnesses that forbid hipMalloc): one frame of

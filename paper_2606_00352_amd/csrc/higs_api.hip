@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "higs_internal.h"
+#include "shcodec.h"
 
 using namespace higs;
 
@@ -229,6 +230,8 @@ void higs_default_params(higs_params* p) {
   p->near_z = 0.2f;
   p->dilation = 0.3f;
   p->sort_mode = HIGS_SORT_ONESWEEP;
+  p->raster_precision = HIGS_RASTER_FP32;
+  p->sh_format = HIGS_SH_FLOAT32;
 }
 
 const char* higs_error_string(int code) {
@@ -255,6 +258,10 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
   if (p.tile_px != kTile || p.mt_tiles_x != kMtTilesX || p.mt_tiles_y != kMtTilesY)
     return HIGS_E_UNSUPPORTED;
   if (p.sh_degree < 0 || p.sh_degree > 3) return HIGS_E_UNSUPPORTED;
+  if (p.raster_precision != HIGS_RASTER_FP32 && p.raster_precision != HIGS_RASTER_FP16)
+    return HIGS_E_INVALID;
+  if (p.sh_format != HIGS_SH_FLOAT32 && p.sh_format != HIGS_SH_PACKED32) return HIGS_E_INVALID;
+  if (p.sh_format == HIGS_SH_PACKED32 && p.sh_degree != 3) return HIGS_E_UNSUPPORTED;
   if (p.sort_mode != HIGS_SORT_SEGMENTED && p.sort_mode != HIGS_SORT_ONESWEEP) return HIGS_E_INVALID;
   if (p.sort_mode == HIGS_SORT_SEGMENTED &&
       ((int64_t)((max_width + kMtW - 1) / kMtW) * ((max_height + kMtH - 1) / kMtH) > kSegMaxMt))
@@ -412,7 +419,8 @@ int higs_project(higs_ctx* c, int64_t n, const float* means, const float* scales
     rc = hip_err(launch_project(n, means, scales, quats, opacities, sh, c->ca, c->pa, c->f_mx,
                                 c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau, c->f_key, c->f_cnt,
                                 c->f_span, c->rec, c->block_sums, c->dc,
-                                (c->debug_flags & HIGS_DEBUG_PROJ_FIELDS) != 0, s));
+                                (c->debug_flags & HIGS_DEBUG_PROJ_FIELDS) != 0,
+                                c->params.sh_format == HIGS_SH_PACKED32, s));
   }
   if (rc) return rc;
   c->stage = 1;
@@ -552,16 +560,26 @@ int higs_raster(higs_ctx* c, float* image, float* T_out, void* stream) {
   c->last_stream = s;
   const uint32_t* v2[2] = {c->vals[0], c->vals[1]};
   int rc;
+  const bool half = c->params.raster_precision == HIGS_RASTER_FP16;
+  const bool count = (c->debug_flags & HIGS_DEBUG_COUNT_EVALS) != 0;
   {
     TimerScope ts(c, HIGS_TIMER_RASTER, s);
-    rc = hip_err(launch_raster(c->ca, c->pa, v2, c->rec, c->batch_tab, c->dc, c->partials,
-                               c->active, c->n_cus, (c->debug_flags & HIGS_DEBUG_COUNT_EVALS) != 0, s));
+    if (half)
+      rc = hip_err(launch_raster16(c->ca, c->pa, v2, c->rec, c->batch_tab, c->dc, c->partials,
+                                   c->active, c->n_cus, count, s));
+    else
+      rc = hip_err(launch_raster(c->ca, c->pa, v2, c->rec, c->batch_tab, c->dc, c->partials,
+                                 c->active, c->n_cus, count, s));
   }
   if (rc) return rc;
   {
     TimerScope ts(c, HIGS_TIMER_MERGE, s);
-    rc = hip_err(launch_merge(c->ca, c->pa, c->batch_first, c->active, c->partials, c->dc, image,
-                              T_out, s));
+    if (half)
+      rc = hip_err(launch_merge16(c->ca, c->pa, c->batch_first, c->active, c->partials, c->dc,
+                                  image, T_out, s));
+    else
+      rc = hip_err(launch_merge(c->ca, c->pa, c->batch_first, c->active, c->partials, c->dc,
+                                image, T_out, s));
   }
   if (rc) return rc;
   c->stage = 4;
@@ -587,6 +605,7 @@ int higs_raster_backward(higs_ctx* c, const float* dL_dimage, const float* dL_dT
   if (!c || !dL_dimage) return HIGS_E_INVALID;
   if (c->n > 0 && (!dmeans || !dscales || !dquats || !dopacities || !dsh)) return HIGS_E_INVALID;
   if (c->stage < 4) return HIGS_E_STATE;
+  if (c->params.raster_precision != HIGS_RASTER_FP32) return HIGS_E_UNSUPPORTED;
   DeviceGuard g(c->device);
   if (!c->bwd_state) {
     if (dalloc(&c->bwd_state, (size_t)c->max_batches * kTilesPerMt * 64) != HIGS_OK ||
@@ -772,6 +791,29 @@ int higs_get_timers(higs_ctx* c, float ms[HIGS_NUM_TIMERS]) {
 }
 
 }  // extern "C"
+
+// ---- packed SH -----------------------------------------------------------------
+extern "C" int64_t higs_sh_packed_bytes(int64_t n) {
+  if (n < 0) return HIGS_E_INVALID;
+  return (int64_t)kShHeaderBytes + 32 * n;
+}
+
+extern "C" int higs_sh_compress(int64_t n, const float* sh, const float* opacities, void* packed,
+                                void* stream) {
+  if (n < 0 || !packed || (n > 0 && (!sh || !opacities))) return HIGS_E_INVALID;
+  if ((reinterpret_cast<uintptr_t>(packed) & 15u) != 0) return HIGS_E_INVALID;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return HIGS_E_HIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return HIGS_E_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t* work = nullptr;
+  if (dalloc(&work, (size_t)kShComps * (1 + 1024) + 1) != HIGS_OK) return HIGS_E_NOMEM;
+  int rc = hip_err(launch_sh_compress(n, sh, opacities, packed, work, prop.multiProcessorCount, s));
+  if (!rc) rc = hip_err(hipStreamSynchronize(s));
+  (void)hipFree(work);
+  return rc;
+}
 
 // ---- allocation-free rendering ------------------------------------------------
 // One frame of the whole path with every intermediate in a static device array

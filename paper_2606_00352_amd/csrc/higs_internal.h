@@ -119,7 +119,7 @@ hipError_t launch_project(int64_t n, const float* means, const float* scales, co
                           float* f_mx, float* f_my, float* f_a, float* f_b, float* f_c,
                           float* f_tau, uint32_t* f_key, uint32_t* f_cnt, uint32_t* f_span,
                           RasterRecord* rec, uint32_t* block_sums, DeviceCounters* dc,
-                          bool all_fields, hipStream_t s);
+                          bool all_fields, bool sh_packed, hipStream_t s);
 
 hipError_t launch_scan(int64_t n, const uint32_t* cnt, uint32_t* block_sums, uint32_t max_pairs,
                        int mt_bits, bool allow_one_word, DeviceCounters* dc, hipStream_t s);
@@ -150,6 +150,16 @@ hipError_t launch_raster(CamArgs cam, ParamArgs prm, const uint32_t* const* vals
                          const RasterRecord* rec, const uint32_t* batch_tab,
                          DeviceCounters* dc, float4* partials, uint32_t* active, int n_cus,
                          bool count_evals, hipStream_t s);
+
+// Half-precision rasteriser and merge; the partials buffer then holds four
+// halves per pixel.
+hipError_t launch_raster16(CamArgs cam, ParamArgs prm, const uint32_t* const* vals2,
+                           const RasterRecord* rec, const uint32_t* batch_tab, DeviceCounters* dc,
+                           void* partials, uint32_t* active, int n_cus, bool count_evals,
+                           hipStream_t s);
+hipError_t launch_merge16(CamArgs cam, ParamArgs prm, const uint32_t* batch_first,
+                          const uint32_t* active, const void* partials, const DeviceCounters* dc,
+                          float* image, float* T_out, hipStream_t s);
 
 hipError_t launch_merge(CamArgs cam, ParamArgs prm, const uint32_t* batch_first,
                         const uint32_t* active, const float4* partials, const DeviceCounters* dc,

@@ -18,6 +18,7 @@
 // sums.
 #include "higs_internal.h"
 #include "predicate.h"
+#include "shcodec.h"
 
 namespace higs {
 
@@ -180,21 +181,35 @@ project_kernel(int64_t n, const float* __restrict__ means, const float* __restri
                uint32_t* __restrict__ f_key, uint32_t* __restrict__ f_cnt,
                uint32_t* __restrict__ f_span, RasterRecord* __restrict__ rec,
                uint32_t* __restrict__ block_sums, DeviceCounters* __restrict__ dc, bool sh_vec4,
-               bool all_fields) {
+               bool all_fields, bool sh_packed) {
   __shared__ uint32_t wave_min[kProjBlock / 64], wave_max[kProjBlock / 64];
   __shared__ uint32_t wave_sums[2][kProjBlock / 64];
+  __shared__ float sh_scale[kShComps];
   const int64_t i = (int64_t)blockIdx.x * kProjBlock + threadIdx.x;
   uint32_t cnt = 0;
   uint32_t kmin = 0xffffffffu, kmax = 0u;
   // degree 3 with a 16-byte aligned sh array: the 48 coefficients (192
   // bytes) are loaded before the geometry, so that the loads overlap its
-  // arithmetic
+  // arithmetic; packed SH: the 32 bytes of the gaussian and, in LDS, the 48
+  // scales of the header
   float4 shv[12];
-  const bool early = sh_vec4 && prm.sh_degree == 3 && i < n;
+  uint32_t shw[8];
+  const bool early = !sh_packed && sh_vec4 && prm.sh_degree == 3 && i < n;
   if (early) {
     const float4* src = reinterpret_cast<const float4*>(sh + 48 * i);
 #pragma unroll
     for (int k = 0; k < 12; ++k) shv[k] = src[k];
+  }
+  if (sh_packed) {
+    if (threadIdx.x < kShComps) sh_scale[threadIdx.x] = sh[threadIdx.x];
+    if (i < n) {
+      const uint4* src = reinterpret_cast<const uint4*>(
+          reinterpret_cast<const char*>(sh) + kShHeaderBytes + 32 * (size_t)i);
+      const uint4 w0 = src[0], w1 = src[1];
+      shw[0] = w0.x, shw[1] = w0.y, shw[2] = w0.z, shw[3] = w0.w;
+      shw[4] = w1.x, shw[5] = w1.y, shw[6] = w1.z, shw[7] = w1.w;
+    }
+    __syncthreads();
   }
   if (i < n) {
     const float3 mean = make_float3(means[3 * i + 0], means[3 * i + 1], means[3 * i + 2]);
@@ -241,7 +256,9 @@ project_kernel(int64_t n, const float* __restrict__ means, const float* __restri
           dz *= inv;
         }
         float3 rgb;
-        if (early) {
+        if (sh_packed) {
+          rgb = sh_colour([&](int k) { return sh_unpack(shw, sh_scale, k); }, 3, dx, dy, dz);
+        } else if (early) {
           const float* c = reinterpret_cast<const float*>(shv);
           rgb = sh_colour([&](int k) { return make_float3(c[3 * k], c[3 * k + 1], c[3 * k + 2]); },
                           3, dx, dy, dz);
@@ -322,7 +339,7 @@ hipError_t launch_project(int64_t n, const float* means, const float* scales, co
                           float* f_mx, float* f_my, float* f_a, float* f_b, float* f_c,
                           float* f_tau, uint32_t* f_key, uint32_t* f_cnt, uint32_t* f_span,
                           RasterRecord* rec, uint32_t* block_sums, DeviceCounters* dc,
-                          bool all_fields, hipStream_t s) {
+                          bool all_fields, bool sh_packed, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   // camera centre, -R^T t, for the SH view direction
   float3 campos;
@@ -333,7 +350,7 @@ hipError_t launch_project(int64_t n, const float* means, const float* scales, co
   hipLaunchKernelGGL(project_kernel, dim3(blocks), dim3(kProjBlock), 0, s, n, means, scales,
                      quats, opac, sh, cam, prm, campos, f_mx, f_my,
                      f_a, f_b, f_c, f_tau, f_key, f_cnt, f_span, rec, block_sums, dc,
-                     (reinterpret_cast<uintptr_t>(sh) & 15u) == 0, all_fields);
+                     (reinterpret_cast<uintptr_t>(sh) & 15u) == 0, all_fields, sh_packed);
   return hipGetLastError();
 }
 

@@ -1,0 +1,256 @@
+// Half-precision rasteriser and merge (sec. 3.5 "Numerical representation",
+// sec. 4.5 "Numerical format"): the reduced-precision mode of the frame path,
+// selected by higs_params.raster_precision = HIGS_RASTER_FP16.
+//
+// The unit is staged as in the float32 kernel (the same records, tile test and
+// mask transpose, raster_common.h), but each gaussian's LDS image is
+// ten halves: the Cholesky factors prescaled by sqrt(log2(e)/2) (so that
+// o exp(-q/2) = exp2(log2 o - q') is one half-precision exp2), c0 = l0' mx +
+// l1' my and c1 = l2' my with the centre relative to the macro-tile centre
+// (every coordinate within a few hundred pixels at most, far inside the half
+// range; q' = u^2 + v^2 is a sum of squares, so rounding cannot make it
+// negative), log2 o, and the colour.  A wave blends two vertically adjacent
+// render tiles at once, one pixel of each per lane, as half2 pairs: u, v and
+// the exponent are three packed fused multiply-adds and two more, the alpha
+// threshold 1/255 is a clamped fused multiply-add on the exponent, and the
+// colour and transmittance are packed accumulators.  As in the paper, the
+// transmittance cut-off is checked per mini-batch of 64 gaussians (the wave
+// leaves the tile pair once every pixel of both tiles is below t_eps) rather
+// than per gaussian; pixels keep blending until then.  Partials are stored as
+// four halves per pixel (8 bytes), merged in float32.
+#include "raster_common.h"
+
+namespace higs {
+
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+
+constexpr int kR16Threads = 512;
+constexpr int kR16Waves = kR16Threads / 64;
+constexpr int kPairs = kTilesPerMt / 2;  // tile t with tile t + 8 (the row below)
+// alpha >= 1/255 <=> exponent >= -log2(255); the clamped ramp
+// t = clamp((E + log2 255) * 2048, 0, 1) is 0 below the threshold and 1 from
+// 1/2048 above it (alpha within 0.04% of 1/255)
+constexpr float kLog2_255 = 7.994353436858858f;
+constexpr float kRamp = 2048.0f;
+
+struct Raster16Lds {
+  h4 ga[kMaxBatch];  // l0', l1', l2', log2 o
+  h4 gb[kMaxBatch];  // c0, c1, r, g
+  h2 gc[kMaxBatch];  // b, -
+  uint64_t masks[kMiniBatches][kTilesPerMt];
+  uint32_t pqueue[kPairs];
+  uint32_t qcount;
+  uint32_t qnext;
+  uint32_t unit;
+};
+
+__device__ __forceinline__ h2 bcast(_Float16 v) { return (h2){v, v}; }
+
+template <bool kCountEvals>
+__global__ void __launch_bounds__(kR16Threads)
+raster16_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ vals0,
+                const uint32_t* __restrict__ vals1, const RasterRecord* __restrict__ rec,
+                const uint32_t* __restrict__ batch_tab, DeviceCounters* __restrict__ dc,
+                h4* __restrict__ partials, uint32_t* __restrict__ active) {
+  __shared__ Raster16Lds L;
+  if (dc->overflow) return;  // the frame stops at a capacity overflow
+  const uint32_t* __restrict__ sorted = dc->sort_final ? vals1 : vals0;
+  const uint32_t n_units = dc->n_batches;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const float eps = prm.t_eps;
+  const _Float16 amax = (_Float16)prm.alpha_max;
+  // this lane's pixels, relative to the macro-tile centre (32, 16)
+  const float pxo = (float)(lane & 7) + 0.5f - 32.0f, pyo = (float)(lane >> 3) + 0.5f - 16.0f;
+
+  for (;;) {
+    if (tid == 0) {
+      L.unit = atomicAdd(&dc->raster_next, 1u);
+      L.qnext = 0;
+    }
+    __syncthreads();
+    const uint32_t u = L.unit;
+    if (u >= n_units) break;
+    const UnitInfo I = unit_info(cam, batch_tab, u);
+
+    // Phase 1: gather, half-precision LDS image, tile test, mask transpose
+    for (int k = wave; k < I.K; k += kR16Waves) {
+      const int j = k * 64 + lane;
+      uint32_t tmask = 0;
+      if (j < I.len) {
+        const uint32_t gid = sorted[I.start + j];
+        const float4* rp = reinterpret_cast<const float4*>(rec + gid);
+        const float4 A = rp[0], B = rp[1], C = rp[2];
+        const float mxr = A.x - (float)I.x0, myr = A.y - (float)I.y0;
+        const float cx = mxr - 32.0f, cy = myr - 16.0f;
+        const float l0k = A.z * kSqrtHalfLog2e, l1k = A.w * kSqrtHalfLog2e;
+        const float l2k = B.x * kSqrtHalfLog2e;
+        L.ga[j] = (h4){(_Float16)l0k, (_Float16)l1k, (_Float16)l2k,
+                       (_Float16)__builtin_amdgcn_logf(B.y)};
+        L.gb[j] = (h4){(_Float16)fmaf(l0k, cx, l1k * cy), (_Float16)(l2k * cy), (_Float16)B.z,
+                       (_Float16)B.w};
+        L.gc[j] = (h2){(_Float16)C.x, (_Float16)0.0f};
+        tmask = tile_overlap(mxr, myr, A.z, A.w, B.x, C.y, I.tiles_x, I.tiles_y);
+      }
+      const uint64_t tm = transpose_tile_masks(tmask, lane);
+      if (lane < kTilesPerMt) L.masks[k][lane] = tm;
+    }
+    __syncthreads();
+    // queue of tile pairs (tile t with t + 8) holding any gaussian; active
+    // bits: the tiles with gaussians of their own
+    uint32_t act = 0;
+    if (wave == 0) {
+      uint64_t hit = 0;
+      if (lane < kTilesPerMt)
+        for (int k = 0; k < I.K; ++k) hit |= L.masks[k][lane];
+      const uint32_t has = (uint32_t)__ballot(lane < kTilesPerMt && hit != 0);
+      const int p = lane & (kPairs - 1);
+      const int t0 = (p >> 3) * 16 + (p & 7);
+      const bool want = lane < kPairs && (((has >> t0) | (has >> (t0 + 8))) & 1u);
+      const uint64_t pm = __ballot(want);
+      if (want) L.pqueue[__popcll(pm & ((1ull << lane) - 1ull))] = (uint32_t)p;
+      if (lane == 0) L.qcount = (uint32_t)__popcll(pm);
+      act = has;
+    }
+    if (tid == 0) active[u] = act;  // lane 0 of wave 0 holds it
+    __syncthreads();
+
+    // Phase 2: waves claim tile pairs
+    for (;;) {
+      uint32_t qi = 0;
+      if (lane == 0) qi = atomicAdd(&L.qnext, 1u);
+      qi = __builtin_amdgcn_readfirstlane(qi);
+      if (qi >= L.qcount) break;
+      const int p = (int)L.pqueue[qi];
+      const int t0 = (p >> 3) * 16 + (p & 7), t1 = t0 + 8;
+      const float px = (float)((t0 & 7) * kTile) + pxo;
+      const float py0 = (float)((t0 >> 3) * kTile) + pyo;
+      const h2 PX = bcast((_Float16)px);
+      const h2 PY = (h2){(_Float16)py0, (_Float16)(py0 + (float)kTile)};
+      const h2 ramp_off = bcast((_Float16)(kLog2_255 * kRamp));
+      const h2 ramp = bcast((_Float16)kRamp);
+      h2 cr = {0, 0}, cg = {0, 0}, cb = {0, 0}, T = {1, 1};
+      uint32_t evals = 0;
+      for (int k = 0; k < I.K; ++k) {
+        uint64_t m = uniform64(L.masks[k][t0] | L.masks[k][t1]);
+        if (kCountEvals) evals += 2u * (uint32_t)__popcll(m);
+        while (m) {
+          const int j = __ffsll((unsigned long long)m) - 1;
+          m &= m - 1ull;
+          const int gi = k * 64 + j;
+          const h4 A = L.ga[gi];  // l0', l1', l2', log2 o
+          const h4 B = L.gb[gi];  // c0, c1, r, g
+          const _Float16 bb = L.gc[gi].x;
+          // u = l0' px + l1' py - c0, v = l2' py - c1, exponent log2 o - u^2 - v^2
+          const h2 U = __builtin_elementwise_fma(bcast(A.x), PX,
+                                                 __builtin_elementwise_fma(bcast(A.y), PY, -bcast(B.x)));
+          const h2 V = __builtin_elementwise_fma(bcast(A.z), PY, -bcast(B.y));
+          const h2 E = __builtin_elementwise_fma(-U, U, __builtin_elementwise_fma(-V, V, bcast(A.w)));
+          const h2 e = __builtin_elementwise_exp2(E);
+          const h2 al = __builtin_elementwise_min(e, bcast(amax));
+          h2 tr = __builtin_elementwise_fma(E, ramp, ramp_off);
+          tr = __builtin_elementwise_min(__builtin_elementwise_max(tr, (h2){0, 0}), (h2){1, 1});
+          const h2 a = al * tr;
+          const h2 w = a * T;
+          cr = __builtin_elementwise_fma(w, bcast(B.z), cr);
+          cg = __builtin_elementwise_fma(w, bcast(B.w), cg);
+          cb = __builtin_elementwise_fma(w, bcast(bb), cb);
+          T = __builtin_elementwise_fma(-a, T, T);
+        }
+        const bool live0 = (float)T.x >= eps, live1 = (float)T.y >= eps;
+        if (__ballot(live0 || live1) == 0) break;
+      }
+      if (kCountEvals && lane == 0) atomicAdd(&dc->n_evals, (unsigned long long)evals);
+      const size_t base = (size_t)u * kTilesPerMt;
+      partials[(base + t0) * 64 + lane] = (h4){cr.x, cg.x, cb.x, T.x};
+      partials[(base + t1) * 64 + lane] = (h4){cr.y, cg.y, cb.y, T.y};
+    }
+    __syncthreads();
+  }
+}
+
+constexpr int kMerge16Threads = 256;
+__global__ void __launch_bounds__(kMerge16Threads)
+merge16_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ batch_first,
+               const uint32_t* __restrict__ active, const h4* __restrict__ partials,
+               const DeviceCounters* __restrict__ dc, float* __restrict__ image,
+               float* __restrict__ T_out) {
+  const int tiles_x = (cam.width + kTile - 1) / kTile;
+  const int tiles_y = (cam.height + kTile - 1) / kTile;
+  const int tile = blockIdx.x * (kMerge16Threads / 64) + (threadIdx.x >> 6);
+  if (tile >= tiles_x * tiles_y) return;
+  const int lane = threadIdx.x & 63;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const uint32_t mt = (uint32_t)((ty / kMtTilesY) * cam.n_mt_x + tx / kMtTilesX);
+  const uint32_t t = (uint32_t)((ty % kMtTilesY) * kMtTilesX + tx % kMtTilesX);
+  const uint32_t nb = dc->overflow ? 0u : dc->n_batches;
+  const uint32_t b0 = min(batch_first[mt], nb), b1 = min(batch_first[mt + 1], nb);
+  const float eps = prm.t_eps;
+  float cr = 0.0f, cg = 0.0f, cb = 0.0f, T = 1.0f;
+  bool stop = false;
+  for (uint32_t c0 = b0; c0 < b1 && !stop; c0 += 64) {
+    const uint32_t bi = c0 + (uint32_t)lane;
+    uint64_t m = __ballot(bi < b1 && ((active[bi] >> t) & 1u));
+    while (m) {
+      const uint32_t b = c0 + (uint32_t)(__ffsll((unsigned long long)m) - 1);
+      m &= m - 1ull;
+      const h4 p = partials[((size_t)b * kTilesPerMt + t) * 64 + lane];
+      if (T >= eps) {
+        cr += T * (float)p.x;
+        cg += T * (float)p.y;
+        cb += T * (float)p.z;
+        T = T * (float)p.w;
+      }
+      if (__ballot(T >= eps) == 0) {
+        stop = true;
+        break;
+      }
+    }
+  }
+  const int x = tx * kTile + (lane & 7), y = ty * kTile + (lane >> 3);
+  if (dc->overflow) cr = cg = cb = T = __builtin_nanf("");
+  if (x < cam.width && y < cam.height) {
+    const size_t pix = (size_t)y * cam.width + x;
+    image[3 * pix + 0] = cr + T * cam.bg[0];
+    image[3 * pix + 1] = cg + T * cam.bg[1];
+    image[3 * pix + 2] = cb + T * cam.bg[2];
+    if (T_out) T_out[pix] = T;
+  }
+}
+
+static int g_r16_per_cu = 0;
+
+hipError_t launch_raster16(CamArgs cam, ParamArgs prm, const uint32_t* const* vals2,
+                           const RasterRecord* rec, const uint32_t* batch_tab, DeviceCounters* dc,
+                           void* partials, uint32_t* active, int n_cus, bool count_evals,
+                           hipStream_t s) {
+  if (g_r16_per_cu == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, raster16_kernel<false>, kR16Threads, 0) !=
+            hipSuccess ||
+        nb < 1)
+      nb = 1;
+    g_r16_per_cu = nb;
+  }
+  h4* p = static_cast<h4*>(partials);
+  if (count_evals)
+    hipLaunchKernelGGL(raster16_kernel<true>, dim3(n_cus * g_r16_per_cu), dim3(kR16Threads), 0, s,
+                       cam, prm, vals2[0], vals2[1], rec, batch_tab, dc, p, active);
+  else
+    hipLaunchKernelGGL(raster16_kernel<false>, dim3(n_cus * g_r16_per_cu), dim3(kR16Threads), 0, s,
+                       cam, prm, vals2[0], vals2[1], rec, batch_tab, dc, p, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge16(CamArgs cam, ParamArgs prm, const uint32_t* batch_first,
+                          const uint32_t* active, const void* partials, const DeviceCounters* dc,
+                          float* image, float* T_out, hipStream_t s) {
+  const int tiles = ((cam.width + kTile - 1) / kTile) * ((cam.height + kTile - 1) / kTile);
+  const int blocks = (tiles + (kMerge16Threads / 64) - 1) / (kMerge16Threads / 64);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(merge16_kernel, dim3(blocks), dim3(kMerge16Threads), 0, s, cam, prm,
+                     batch_first, active, static_cast<const h4*>(partials), dc, image, T_out);
+  return hipGetLastError();
+}
+
+}  // namespace higs

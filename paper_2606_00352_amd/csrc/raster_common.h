@@ -171,6 +171,27 @@ __device__ __forceinline__ uint32_t stage_unit(RasterLds& L, const UnitInfo& I,
   return act32;
 }
 
+// The 64 x 32 bit matrix of a mini-batch (lane = gaussian, bit = tile)
+// transposed: lane t < 32 gets tile t's 64-bit gaussian mask (the butterfly of
+// stage_unit: a 32 x 32 transpose inside each half wave, then the halves
+// joined).  All 64 lanes take part.
+__device__ __forceinline__ uint64_t transpose_tile_masks(uint32_t tmask, int lane) {
+  uint32_t x = tmask;
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    const int j = 16 >> s;
+    const uint32_t m = s == 0 ? 0x0000FFFFu : s == 1 ? 0x00FF00FFu : s == 2 ? 0x0F0F0F0Fu
+                     : s == 3 ? 0x33333333u : 0x55555555u;
+    const bool upper = (lane & j) != 0;
+    const uint32_t y = (uint32_t)__shfl_xor((int)x, j, 64);
+    const uint32_t ys = __builtin_amdgcn_alignbit(y, y, upper ? j : 32 - j);
+    const uint32_t keep = upper ? ~m : m;
+    x = (x & keep) | (ys & ~keep);
+  }
+  const uint32_t x_hi = (uint32_t)__shfl_xor((int)x, 32, 64);
+  return ((uint64_t)x_hi << 32) | x;
+}
+
 // Next tile of the unit's queue for this wave (uniform), or -1.
 __device__ __forceinline__ int next_tile(RasterLds& L, int lane) {
   uint32_t qi = 0;

@@ -20,6 +20,8 @@ OVF_PAIRS, OVF_BATCHES = 1, 2
 DBG_PROJ, DBG_RECORDS, DBG_PAIRS, DBG_SORTED, DBG_MT_OFFSETS, DBG_BATCHES, DBG_ACTIVE, DBG_PARTIALS = range(1, 9)
 DEBUG_KEEP_PAIRS, DEBUG_COUNT_EVALS, DEBUG_PROJ_FIELDS, DEBUG_TWO_WORD_PAIRS = 1, 2, 4, 8
 SORT_SEGMENTED, SORT_ONESWEEP = 0, 1
+RASTER_FP32, RASTER_FP16 = 0, 1
+SH_FLOAT32, SH_PACKED32 = 0, 1
 TIMER_NAMES = ("project", "scan", "fill", "sort", "batch", "raster", "merge")
 
 # every symbol include/higs.h declares
@@ -28,7 +30,8 @@ EXPORTS = ("higs_default_params", "higs_ctx_create", "higs_ctx_destroy", "higs_p
            "higs_set_debug", "higs_debug_copy", "higs_set_timing", "higs_get_timers",
            "higs_error_string", "higs_raster_backward", "higs_ctx_footprint",
            "higs_server_create", "higs_server_destroy", "higs_server_add_scene", "higs_server_submit",
-           "higs_server_poll", "higs_server_get_stats", "higs_render_noalloc")
+           "higs_server_poll", "higs_server_get_stats", "higs_render_noalloc", "higs_sh_packed_bytes",
+           "higs_sh_compress")
 
 
 class HigsError(RuntimeError):
@@ -42,7 +45,8 @@ class Params(ctypes.Structure):
                 ("mt_tiles_y", ctypes.c_int32), ("batch_cap", ctypes.c_int32),
                 ("sh_degree", ctypes.c_int32), ("alpha_max", ctypes.c_float),
                 ("t_eps", ctypes.c_float), ("near_z", ctypes.c_float),
-                ("dilation", ctypes.c_float), ("sort_mode", ctypes.c_int32)]
+                ("dilation", ctypes.c_float), ("sort_mode", ctypes.c_int32),
+                ("raster_precision", ctypes.c_int32), ("sh_format", ctypes.c_int32)]
 
 
 class CameraC(ctypes.Structure):
@@ -115,6 +119,8 @@ def lib():
             "higs_server_poll": (ctypes.c_int, [P, P, i32]),
             "higs_server_get_stats": (ctypes.c_int, [P, P]),
             "higs_render_noalloc": (ctypes.c_int, [i64, P, P, P, P, P, P, P, P, P]),
+            "higs_sh_packed_bytes": (i64, [i64]),
+            "higs_sh_compress": (ctypes.c_int, [i64, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -452,6 +458,20 @@ def render(ctx: Context, tensors, cam, with_T: bool = True, stream=None, check: 
     else:
         ctx.render(*tensors, cam, image, T, stream)
     return image, T
+
+
+def sh_compress(sh, opacities, stream=None):
+    """The 32-byte packed SH of sh [n, 16, 3] (higs_sh_compress): an int32
+    device tensor of higs_sh_packed_bytes(n) bytes (a header of 48 float32
+    scales, then 8 words per gaussian); pass it as the scene's SH to a
+    context with sh_format=SH_PACKED32."""
+    import torch
+    n = int(sh.shape[0])
+    nbytes = int(lib().higs_sh_packed_bytes(n))
+    out = torch.empty(nbytes // 4, dtype=torch.int32, device=sh.device)
+    _check(lib().higs_sh_compress(n, _ptr(sh.contiguous()), _ptr(opacities.contiguous()), out.data_ptr(),
+                                  _stream(stream)), "higs_sh_compress")
+    return out
 
 
 def render_noalloc(tensors, cam, image, T=None, stream=None):

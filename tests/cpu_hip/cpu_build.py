@@ -82,7 +82,7 @@ class Frame:
 
 
 def run_frames(scene, cams, max_pairs, max_batches, sort_mode=1, batch_cap=1024, n_cus=2,
-               entry=0, uses=None, timeout=600, workdir=None):
+               entry=0, uses=None, timeout=600, workdir=None, precision=0, sh_format=0):
     """Renders `scene` (numpy arrays) for each camera; returns a list of Frame
     with rc, n_visible, n_pairs, n_batches, overflow, image, T, and (when the
     frame did not overflow) sorted keys/ids and the batch table."""
@@ -96,7 +96,8 @@ def run_frames(scene, cams, max_pairs, max_batches, sort_mode=1, batch_cap=1024,
             a.tofile(os.path.join(work, name))
         uses = uses or [n] * len(cams)
         with open(os.path.join(work, "job.txt"), "w") as f:
-            f.write(f"{n} {max_pairs} {max_batches} {sort_mode} {batch_cap} {n_cus} {entry}\n")
+            f.write(f"{n} {max_pairs} {max_batches} {sort_mode} {batch_cap} {n_cus} {entry} {precision} "
+                    f"{sh_format}\n")
             for c, u in zip(cams, uses):
                 w = np.asarray(c.world_to_cam, np.float32).reshape(-1)
                 bg = getattr(c, "background", (0.0, 0.0, 0.0))
@@ -110,11 +111,16 @@ def run_frames(scene, cams, max_pairs, max_batches, sort_mode=1, batch_cap=1024,
         if r.returncode != 0:
             raise RuntimeError(f"frame driver failed ({r.returncode}):\n{r.stderr[-8000:]}")
         frames = []
+        packed = None
+        if os.path.exists(os.path.join(out, "packed")):
+            packed = np.fromfile(os.path.join(out, "packed"), np.uint8)
         lines = open(os.path.join(out, "counts.txt")).read().split("\n")
         for k, c in enumerate(cams):
             fr = Frame()
             rc, vis, pairs, batches, evals, ovf = (int(x) for x in lines[k].split())
             fr.rc, fr.n_visible, fr.n_pairs, fr.n_batches, fr.overflow = rc, vis, pairs, batches, ovf
+            fr.n_evaluations = evals
+            fr.packed = packed
             pre = os.path.join(out, f"f{k}_")
             fr.image = np.fromfile(pre + "image", np.float32).reshape(c.height, c.width, 3)
             fr.T = np.fromfile(pre + "T", np.float32).reshape(c.height, c.width)

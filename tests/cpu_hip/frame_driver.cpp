@@ -12,6 +12,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <sys/mman.h>
+
 #include <string>
 #include <vector>
 
@@ -52,8 +54,9 @@ int main(int argc, char** argv) {
   if (!jf) return 2;
   long long n, max_pairs, max_batches;
   int sort_mode, batch_cap, n_cus, entry;
-  if (fscanf(jf, "%lld %lld %lld %d %d %d %d", &n, &max_pairs, &max_batches, &sort_mode,
-             &batch_cap, &n_cus, &entry) != 7)
+  int precision = 0, sh_format = 0;
+  if (fscanf(jf, "%lld %lld %lld %d %d %d %d %d %d", &n, &max_pairs, &max_batches, &sort_mode,
+             &batch_cap, &n_cus, &entry, &precision, &sh_format) != 9)
     return 2;
   std::vector<float> means = load(in + "/means", (size_t)n * 3);
   std::vector<float> scales = load(in + "/scales", (size_t)n * 3);
@@ -64,6 +67,18 @@ int main(int argc, char** argv) {
   higs_default_params(&p);
   p.sort_mode = sort_mode;
   p.batch_cap = batch_cap;
+  p.raster_precision = precision;
+  p.sh_format = sh_format;
+  // packed SH: compressed once by the library, written out for the tests
+  std::vector<unsigned char> packed;
+  if (sh_format == HIGS_SH_PACKED32) {
+    packed.resize((size_t)higs_sh_packed_bytes(n));
+    if (higs_sh_compress(n, sh.data(), opac.data(), packed.data(), nullptr)) return 3;
+    save(out + "/packed", packed.data(), packed.size());
+  }
+  const float* sh_in = sh_format == HIGS_SH_PACKED32
+                           ? reinterpret_cast<const float*>(packed.data())
+                           : sh.data();
   higs_ctx* ctx = nullptr;
   int max_w = 1, max_h = 1;
   std::vector<higs_camera> cams;
@@ -97,7 +112,19 @@ int main(int argc, char** argv) {
   for (size_t f = 0; f < cams.size(); ++f) {
     const higs_camera& c = cams[f];
     const size_t npx = (size_t)c.width * c.height;
-    std::vector<float> image(npx * 3, -7.0f), T(npx, -7.0f);
+    // outputs in a shared mapping: with CPUHIP_PROCS > 1 the workgroups that
+    // write them run in other processes
+    float* image_p = static_cast<float*>(mmap(nullptr, npx * 16, PROT_READ | PROT_WRITE,
+                                              MAP_SHARED | MAP_ANONYMOUS, -1, 0));
+    if (image_p == MAP_FAILED) return 2;
+    float* T_p = image_p + npx * 3;
+    for (size_t q = 0; q < npx * 4; ++q) image_p[q] = -7.0f;
+    struct View {
+      float* p;
+      size_t n;
+      float* data() { return p; }
+      size_t size() const { return n; }
+    } image{image_p, npx * 3}, T{T_p, npx};
     int rc = 0;
     higs_counts cn{};
     const std::string pre = out + "/f" + std::to_string(f) + "_";
@@ -105,7 +132,7 @@ int main(int argc, char** argv) {
       // stage by stage, reading back each stage's output as soon as it exists,
       // so that a failure names its stage
       rc = higs_project(ctx, uses[f], means.data(), scales.data(), quats.data(), opac.data(),
-                        sh.data(), &c, nullptr);
+                        sh_in, &c, nullptr);
       if (!rc) rc = higs_bin_sort(ctx, nullptr);
       if (!rc && higs_get_counts(ctx, &cn)) return 4;
       if (!rc && !cn.overflow && (debug_flags & HIGS_DEBUG_KEEP_PAIRS)) {
@@ -138,6 +165,7 @@ int main(int argc, char** argv) {
     }
     save(pre + "image", image.data(), image.size() * 4);
     save(pre + "T", T.data(), T.size() * 4);
+    munmap(image_p, npx * 16);
     fprintf(summary, "%d %lld %lld %lld %lld %u\n", rc, (long long)cn.n_visible,
             (long long)cn.n_pairs, (long long)cn.n_batches, (long long)cn.n_evaluations,
             cn.overflow);

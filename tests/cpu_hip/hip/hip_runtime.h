@@ -21,7 +21,12 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <sys/mman.h>
+#include <sys/wait.h>
+#include <unistd.h>
+
 #include <atomic>
+#include <map>
 #include <barrier>
 #include <chrono>
 #include <condition_variable>
@@ -67,6 +72,7 @@ struct __attribute__((aligned(16))) uint4 {
   unsigned x, y, z, w;
 };
 inline float2 make_float2(float a, float b) { return float2{a, b}; }
+inline uint4 make_uint4(unsigned a, unsigned b, unsigned c, unsigned d) { return uint4{a, b, c, d}; }
 inline float4 make_float4(float a, float b, float c, float d) { return float4{a, b, c, d}; }
 
 namespace cpuhip {
@@ -102,7 +108,9 @@ inline int wave_id() {
 }
 
 // All present lanes' 64-bit values; `mask` gets the present lanes.
+inline void reset_spin();
 inline void wave_exchange(uint64_t v, uint64_t out[kWave], uint64_t* mask) {
+  reset_spin();
   Wave& w = *tl_blk->waves[wave_id()];
   const int l = lane_id();
   w.slot[l] = v;
@@ -191,9 +199,19 @@ class Pool {
   uint64_t gen_ = 0;
   bool stop_ = false;
 };
-inline Pool& pool() {
-  static Pool p;
+inline Pool*& pool_ptr() {
+  static Pool* p = new Pool();
   return p;
+}
+inline Pool& pool() { return *pool_ptr(); }
+
+// CPUHIP_PROCS = k > 1: the workgroups of a launch run in k forked processes
+// at once (workgroup w in process w mod k), so that workgroups of a
+// persistent kernel really interleave; device memory is then a shared mapping
+// (no AddressSanitizer redzones), and every process has its own LDS.
+inline int procs() {
+  static int k = getenv("CPUHIP_PROCS") ? atoi(getenv("CPUHIP_PROCS")) : 1;
+  return k;
 }
 
 template <class... A, class... P>
@@ -204,9 +222,29 @@ void launch(void (*k)(P...), dim3 grid, dim3 block, size_t shmem, A... args) {
   g_block_dim = block;
   g_grid_dim = grid;
   const unsigned nw = (nt + kWave - 1) / kWave;
+  const unsigned n_blocks = grid.x * grid.y * grid.z;
+  const int np = procs() > 1 && n_blocks > 1 ? procs() : 1;
+  std::vector<pid_t> kids;
+  int me = 0;
+  if (np > 1) {
+    fflush(stdout);
+    fflush(stderr);
+    for (int c = 1; c < np; ++c) {
+      const pid_t pid = fork();
+      if (pid == 0) {
+        me = c;
+        pool_ptr() = new Pool();  // the parent's worker threads do not exist here
+        kids.clear();
+        break;
+      }
+      kids.push_back(pid);
+    }
+  }
+  unsigned flat = 0;
   for (unsigned bz = 0; bz < grid.z; ++bz)
     for (unsigned by = 0; by < grid.y; ++by)
-      for (unsigned bx = 0; bx < grid.x; ++bx) {
+      for (unsigned bx = 0; bx < grid.x; ++bx, ++flat) {
+        if ((int)(flat % (unsigned)np) != me) continue;
         Block B;
         std::barrier<> bbar((ptrdiff_t)nt);
         B.bar = &bbar;
@@ -234,6 +272,17 @@ void launch(void (*k)(P...), dim3 grid, dim3 block, size_t shmem, A... args) {
         for (Wave* w : B.waves) delete w;
         for (auto* b : wbars) delete b;
       }
+  if (np > 1) {
+    if (me != 0) _exit(0);
+    for (pid_t pid : kids) {
+      int st = 0;
+      waitpid(pid, &st, 0);
+      if (!WIFEXITED(st) || WEXITSTATUS(st) != 0) {
+        fprintf(stderr, "cpuhip: a workgroup process failed\n");
+        abort();
+      }
+    }
+  }
 }
 
 }  // namespace cpuhip
@@ -243,7 +292,10 @@ void launch(void (*k)(P...), dim3 grid, dim3 block, size_t shmem, A... args) {
 #define blockDim (cpuhip::g_block_dim)
 #define gridDim (cpuhip::g_grid_dim)
 
-inline void __syncthreads() { cpuhip::tl_blk->bar->arrive_and_wait(); }
+inline void __syncthreads() {
+  cpuhip::reset_spin();
+  cpuhip::tl_blk->bar->arrive_and_wait();
+}
 inline int __syncthreads_or(int p) {
   cpuhip::Block& b = *cpuhip::tl_blk;
   const int ph = cpuhip::tl_phase;
@@ -411,7 +463,22 @@ inline T atomicCAS(T* p, T cmp, T v) {
   __atomic_compare_exchange_n(p, &cmp, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST);
   return cmp;
 }
-#define __hip_atomic_load(p, order, scope) __atomic_load_n((p), __ATOMIC_SEQ_CST)
+namespace cpuhip {
+// A work-item that keeps loading the same word is waiting for another
+// workgroup: after a while it sleeps between loads, so that the GPU code's
+// spin bounds (sized for GPU speed) stay long enough at emulation speed.
+// (atomic loads since the work-item last met its wave or workgroup)
+inline thread_local unsigned tl_spin_count = 0;
+template <class T>
+inline T spin_load(const T* p) {
+  if (++tl_spin_count > 4096) usleep(20);
+  return __atomic_load_n(p, __ATOMIC_SEQ_CST);
+}
+}  // namespace cpuhip
+namespace cpuhip {
+inline void reset_spin() { tl_spin_count = 0; }
+}  // namespace cpuhip
+#define __hip_atomic_load(p, order, scope) cpuhip::spin_load(p)
 #define __hip_atomic_store(p, v, order, scope) __atomic_store_n((p), (v), __ATOMIC_SEQ_CST)
 #define __hip_atomic_fetch_add(p, v, order, scope) __atomic_fetch_add((p), (v), __ATOMIC_SEQ_CST)
 #define __hip_atomic_fetch_or(p, v, order, scope) __atomic_fetch_or((p), (v), __ATOMIC_SEQ_CST)
@@ -455,11 +522,32 @@ inline double now_ms() {
 }
 }  // namespace cpuhip
 
+namespace cpuhip {
+inline std::map<void*, size_t>& shared_maps() {
+  static std::map<void*, size_t> m;
+  return m;
+}
+}  // namespace cpuhip
 inline hipError_t hipMalloc(void** p, size_t n) {
-  *p = aligned_alloc(256, (n + 255) / 256 * 256);
+  const size_t bytes = (n + 255) / 256 * 256;
+  if (cpuhip::procs() > 1) {  // visible to the workgroup processes
+    void* q = mmap(nullptr, bytes ? bytes : 256, PROT_READ | PROT_WRITE, MAP_SHARED | MAP_ANONYMOUS,
+                   -1, 0);
+    if (q == MAP_FAILED) return hipErrorOutOfMemory;
+    cpuhip::shared_maps()[q] = bytes ? bytes : 256;
+    *p = q;
+    return hipSuccess;
+  }
+  *p = aligned_alloc(256, bytes);
   return *p ? hipSuccess : hipErrorOutOfMemory;
 }
 inline hipError_t hipFree(void* p) {
+  auto it = cpuhip::shared_maps().find(p);
+  if (it != cpuhip::shared_maps().end()) {
+    munmap(p, it->second);
+    cpuhip::shared_maps().erase(it);
+    return hipSuccess;
+  }
   free(p);
   return hipSuccess;
 }

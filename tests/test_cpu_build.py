@@ -58,3 +58,43 @@ def test_capacity_overflow_stops_the_frame(orc):
     o = orc.frame(sc, cam)
     d = np.abs(ok.image.astype(np.float64) - o.image)
     assert d[o.amb == 0].max() <= 2e-4 and d.mean() <= 1e-5
+
+
+def _psnr(a, b):
+    mse = float(np.mean((np.asarray(a, np.float64) - np.asarray(b, np.float64)) ** 2))
+    return 10.0 * np.log10(1.0 / mse) if mse > 0 else np.inf
+
+
+def test_packed_sh_matches_the_oracle_codec(orc):
+    """higs_sh_compress writes the oracle codec's scales and words bit for bit,
+    and the projection's colour from them is the oracle's colour from the
+    decoded coefficients (the image within the float32 tolerance)."""
+    from oracle import shcodec
+    cpu = _cpu()
+    sc, cams = scenes.config0()
+    cam = cams[0]
+    fr = cpu.run_frames(sc, [cam], max_pairs=1 << 17, max_batches=1 << 12, sh_format=1)[0]
+    s, w = shcodec.compress(sc.sh, sc.opacities)
+    assert np.array_equal(fr.packed[:256].view(np.float32)[:48], s)
+    assert np.array_equal(fr.packed[256:].view(np.uint32).reshape(-1, 8), w)
+    dec = scenes.Scene(sc.means, sc.scales, sc.quats, sc.opacities,
+                       shcodec.decompress(s, w).reshape(sc.sh.shape))
+    o = orc.frame(dec, cam)
+    d = np.abs(fr.image.astype(np.float64) - o.image)
+    assert d[o.amb == 0].max() <= 2e-4 and d.mean() <= 1e-5
+
+
+def test_half_precision_raster(orc):
+    """The reduced-precision mode: the same pairs, order and batches as the
+    float32 mode, and an image within the paper's fidelity range of the oracle
+    (its fp16 renderer is 67 dB from the float32 one)."""
+    cpu = _cpu()
+    sc, cams = scenes.config0()
+    cam = cams[0]
+    fr = cpu.run_frames(sc, [cam], max_pairs=1 << 17, max_batches=1 << 12, precision=1)[0]
+    o = orc.frame(sc, cam)
+    want = (o.sorted_mt.astype(np.uint64) << np.uint64(32)) | o.sorted_key.astype(np.uint64)
+    assert np.array_equal(fr.keys, want) and np.array_equal(fr.ids, o.sorted_gid.astype(np.uint32))
+    assert np.array_equal(fr.batches.astype(np.int64), o.batch_tab.astype(np.int64))
+    assert _psnr(fr.image, o.image) >= 55.0
+    assert np.all(np.isfinite(fr.image)) and np.all((fr.T >= 0) & (fr.T <= 1))
