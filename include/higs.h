@@ -91,7 +91,10 @@ typedef struct {
   int32_t sort_mode;  /* HIGS_SORT_ONESWEEP (default) or HIGS_SORT_SEGMENTED */
   int32_t raster_precision; /* HIGS_RASTER_FP32 (default) or HIGS_RASTER_FP16 */
   int32_t sh_format;  /* HIGS_SH_FLOAT32 (default) or HIGS_SH_PACKED32 */
+  int32_t max_views;  /* views one frame of higs_render_views may hold, 1..HIGS_MAX_VIEWS (1) */
 } higs_params;
+
+#define HIGS_MAX_VIEWS 64
 
 /* Reduced-precision mode (sec. 3.5 "Numerical representation" and sec. 4.5
  * "Numerical format"): HIGS_RASTER_FP16 rasterises in packed half precision
@@ -200,6 +203,27 @@ int higs_raster(higs_ctx* ctx, float* image, float* T_out, void* stream);
 int higs_render(higs_ctx* ctx, int64_t n, const float* means, const float* scales,
                 const float* quats, const float* opacities, const float* sh,
                 const higs_camera* cam, float* image, float* T_out, void* stream);
+
+/* Several views in one frame: every stage runs once, in one launch per kernel,
+ * for n_views cameras of one image size, each with its own scene arrays and
+ * image (serving many requests per launch).  View v's gaussians and
+ * macro-tiles get ranges of their own in the frame (the pair keys carry the
+ * view in their macro-tile field), so the emission, the sort, the batch split
+ * and the rasteriser treat the views as one larger frame; each image is the
+ * one higs_render gives for that view alone, bit for bit.  The context must be
+ * created with params->max_views >= n_views; max_gaussians bounds each view's
+ * n; max_pairs and max_batches bound the frame's totals (all views).  Every
+ * view's camera must have the size of views[0].camera (else HIGS_E_INVALID).
+ * Not with the segmented sort mode, and not followed by higs_raster_backward.
+ * The views array (host) is read before the call returns. */
+typedef struct {
+  int64_t n;                /* gaussians of this view's scene */
+  const float *means, *scales, *quats, *opacities, *sh;  /* device, as higs_project */
+  higs_camera camera;       /* host */
+  float* image;             /* device [H, W, 3] */
+  float* T_out;             /* device [H, W] or NULL */
+} higs_view;
+int higs_render_views(higs_ctx* ctx, int32_t n_views, const higs_view* views, void* stream);
 
 /* Adjoint of the last frame rendered on ctx (the paper is forward-only; its
  * Forward-only paragraph outlines this backward: the post-blend merge of

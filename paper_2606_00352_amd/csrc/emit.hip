@@ -153,11 +153,12 @@ hipError_t launch_scan(int64_t n, const uint32_t* cnt, uint32_t* block_sums, uin
 // the group is loaded first; the group's block offsets are its chunk's offset
 // plus a workgroup scan of the chunk's block sums (one per thread); then each
 // block's pairs are written at its offset plus the wave prefix sums.
-constexpr int kFillBlocks = 4;
+constexpr int kFillBlocks = kFillGroup;
 static_assert(kScanChunk == kProjBlock && kScanChunk % kFillBlocks == 0,
               "one chunk block per fill thread; a fill group never straddles chunks");
 __global__ void __launch_bounds__(kProjBlock)
-fill_kernel(int64_t n, CamArgs cam, const float* __restrict__ f_mx, const float* __restrict__ f_my,
+fill_kernel(int64_t n, CamArgs cam, int64_t n_pad, uint32_t n_mt,
+            const float* __restrict__ f_mx, const float* __restrict__ f_my,
             const float* __restrict__ f_a, const float* __restrict__ f_b,
             const float* __restrict__ f_c, const float* __restrict__ f_tau,
             const uint32_t* __restrict__ f_key, const uint32_t* __restrict__ f_cnt,
@@ -204,6 +205,9 @@ fill_kernel(int64_t n, CamArgs cam, const float* __restrict__ f_mx, const float*
   const uint32_t dmin = dc->key_min;
   const uint32_t dbits = depth_bits(dmin, dc->key_max);
   const uint32_t ish = dc->id_shift;
+  // the view's first macro-tile: views own whole fill groups of blocks, so
+  // one uniform division serves the group
+  const uint32_t mt0 = (uint32_t)(blk0 / (n_pad / kProjBlock)) * n_mt;
 #pragma unroll
   for (int k = 0; k < kFillBlocks; ++k) {
     if (__ballot(cnt[k] > 0) == 0) continue;  // whole wave invisible in this block
@@ -212,10 +216,10 @@ fill_kernel(int64_t n, CamArgs cam, const float* __restrict__ f_mx, const float*
     if (cnt[k] == 0) continue;
     const int64_t i = (blk0 + k) * kProjBlock + threadIdx.x;
     const uint64_t depth = (uint64_t)(key[k] - dmin);
-    const uint32_t gid = (uint32_t)i;
+    const uint32_t gid = (uint32_t)i;  // virtual: the view's range, then the gaussian
     auto emit = [&](uint32_t mt) {
       if (at < max_pairs) {
-        const uint64_t key = ((uint64_t)mt << dbits) | depth;
+        const uint64_t key = ((uint64_t)(mt0 + mt) << dbits) | depth;
         if (ish) {
           keys[at] = (key << ish) | gid;
         } else {
@@ -240,7 +244,8 @@ fill_kernel(int64_t n, CamArgs cam, const float* __restrict__ f_mx, const float*
   }
 }
 
-hipError_t launch_fill(int64_t n, CamArgs cam, const float* f_mx, const float* f_my,
+hipError_t launch_fill(int64_t n, CamArgs cam, int64_t n_pad, uint32_t n_mt, const float* f_mx,
+                       const float* f_my,
                        const float* f_a, const float* f_b, const float* f_c, const float* f_tau,
                        const uint32_t* f_key, const uint32_t* f_cnt, const uint32_t* f_span,
                        const uint32_t* block_sums, uint32_t max_pairs,
@@ -248,9 +253,9 @@ hipError_t launch_fill(int64_t n, CamArgs cam, const float* f_mx, const float* f
   if (n <= 0) return hipSuccess;
   const int64_t n_blocks = (n + kProjBlock - 1) / kProjBlock;
   const unsigned blocks = (unsigned)((n_blocks + kFillBlocks - 1) / kFillBlocks);
-  hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(kProjBlock), 0, s, n, cam, f_mx, f_my, f_a,
-                     f_b, f_c, f_tau, f_key, f_cnt, f_span, block_sums, max_pairs, dc, keys,
-                     vals);
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(kProjBlock), 0, s, n, cam, n_pad, n_mt, f_mx,
+                     f_my, f_a, f_b, f_c, f_tau, f_key, f_cnt, f_span, block_sums, max_pairs, dc,
+                     keys, vals);
   return hipGetLastError();
 }
 

@@ -17,6 +17,8 @@
 
 using namespace higs;
 
+constexpr int kViewRing = 4;
+
 struct higs_ctx {
   int device = 0;
   int n_cus = 0;
@@ -59,6 +61,16 @@ struct higs_ctx {
   int64_t n = 0;
   int stage = 0;  // 1 projected, 2 sorted, 3 batched, 4 rastered
   int n_mt = 0, n_passes = 0;
+  // views of the frame (a single-view frame: n_views = 1)
+  int n_views = 1;
+  int64_t n_pad = 0;    // virtual gaussians per view
+  int64_t n_virt = 0;   // n_views * n_pad
+  int n_mt_all = 0;     // n_views * n_mt
+  Views views{};
+  ViewArgs* view_table = nullptr;  // [max_views] device copy of the views
+  ViewArgs* view_stage = nullptr;  // [kViewRing][max_views] pinned host slots
+  hipEvent_t view_ev[kViewRing] = {};
+  int view_slot = 0;
   uint32_t epoch = 1;  // sort look-back epochs
   hipStream_t last_stream = nullptr;
   int debug_flags = 0;
@@ -129,19 +141,31 @@ void free_all(higs_ctx* c) {
                   c->dbg_keys, c->dbg_vals, c->hist, c->plan, c->status, c->mt_off,
                   c->batch_first, c->batch_tab, c->active, c->partials, c->dc,
                   c->bwd_state, c->dgeo, c->seg_count, c->seg_cursor, c->seg_chunk_off,
-                  c->seg_blk_off};
+                  c->seg_blk_off, c->view_table};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
+  if (c->view_stage) (void)hipHostFree(c->view_stage);
+  for (hipEvent_t& e : c->view_ev)
+    if (e) (void)hipEventDestroy(e);
   free_events(c);
 }
 
 // Every device buffer of a context and its element count, in one place:
 // higs_ctx_create allocates them, higs_ctx_footprint adds them up, and the
 // allocation-free entry point lays them out in its static scratch array.
+// A view's range of virtual gaussians: whole fill groups of projection blocks
+// (the emission takes the view from the group's first block).
+int64_t pad_blocks(int64_t n) {
+  constexpr int64_t q = (int64_t)kProjBlock * kFillGroup;
+  return (n + q - 1) / q * q;
+}
+
 // Needs max_g, max_pairs, max_batches, max_mt and max_tiles set.
 template <class F>
 void for_each_buffer(higs_ctx* c, F&& f) {
-  const size_t G = (size_t)c->max_g, P = (size_t)c->max_pairs, B = (size_t)c->max_batches;
+  // per-gaussian arrays hold max_views ranges of max_g, each padded
+  const size_t G = (size_t)c->params.max_views * (size_t)pad_blocks(c->max_g);
+  const size_t P = (size_t)c->max_pairs, B = (size_t)c->max_batches;
   const size_t nblk = (G + kProjBlock - 1) / kProjBlock;
   const size_t mt = (size_t)c->max_mt;
   f(&c->f_mx, G);
@@ -172,6 +196,7 @@ void for_each_buffer(higs_ctx* c, F&& f) {
   f(&c->seg_cursor, mt);
   f(&c->seg_chunk_off, mt + 1);
   f(&c->seg_blk_off, mt + 1);
+  f(&c->view_table, (size_t)c->params.max_views);
 }
 
 void set_capacities(higs_ctx* c, int64_t max_gaussians, int64_t max_pairs, int64_t max_batches,
@@ -181,7 +206,8 @@ void set_capacities(higs_ctx* c, int64_t max_gaussians, int64_t max_pairs, int64
   c->max_batches = max_batches;
   c->max_w = max_width;
   c->max_h = max_height;
-  c->max_mt = ((max_width + kMtW - 1) / kMtW) * ((max_height + kMtH - 1) / kMtH);
+  c->max_mt = ((max_width + kMtW - 1) / kMtW) * ((max_height + kMtH - 1) / kMtH) *
+              (c->params.max_views > 0 ? c->params.max_views : 1);
   c->max_tiles = (uint32_t)((max_pairs + kSortTile - 1) / kSortTile);
 }
 
@@ -232,6 +258,7 @@ void higs_default_params(higs_params* p) {
   p->sort_mode = HIGS_SORT_ONESWEEP;
   p->raster_precision = HIGS_RASTER_FP32;
   p->sh_format = HIGS_SH_FLOAT32;
+  p->max_views = 1;
 }
 
 const char* higs_error_string(int code) {
@@ -262,6 +289,8 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
     return HIGS_E_INVALID;
   if (p.sh_format != HIGS_SH_FLOAT32 && p.sh_format != HIGS_SH_PACKED32) return HIGS_E_INVALID;
   if (p.sh_format == HIGS_SH_PACKED32 && p.sh_degree != 3) return HIGS_E_UNSUPPORTED;
+  if (p.max_views < 1 || p.max_views > HIGS_MAX_VIEWS) return HIGS_E_INVALID;
+  if (p.max_views > 1 && p.sort_mode == HIGS_SORT_SEGMENTED) return HIGS_E_UNSUPPORTED;
   if (p.sort_mode != HIGS_SORT_SEGMENTED && p.sort_mode != HIGS_SORT_ONESWEEP) return HIGS_E_INVALID;
   if (p.sort_mode == HIGS_SORT_SEGMENTED &&
       ((int64_t)((max_width + kMtW - 1) / kMtW) * ((max_height + kMtH - 1) / kMtH) > kSegMaxMt))
@@ -306,6 +335,14 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
   ok = ok && hipMemsetAsync(c->dc, 0, sizeof(DeviceCounters), init) == hipSuccess;
   ok = ok && hipStreamSynchronize(init) == hipSuccess;
   if (init) (void)hipStreamDestroy(init);
+  // several views: pinned slots from which each frame's view table is copied
+  if (ok && p.max_views > 1) {
+    ok = hipHostMalloc(reinterpret_cast<void**>(&c->view_stage),
+                       sizeof(ViewArgs) * (size_t)p.max_views * kViewRing,
+                       hipHostMallocDefault) == hipSuccess;
+    for (int k = 0; ok && k < kViewRing; ++k)
+      ok = hipEventCreateWithFlags(&c->view_ev[k], hipEventDisableTiming) == hipSuccess;
+  }
   if (!ok) {
     free_all(c);
     delete c;
@@ -317,10 +354,12 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
 
 int64_t higs_ctx_footprint(const higs_params* params, int64_t max_gaussians, int64_t max_pairs,
                            int64_t max_batches, int32_t max_width, int32_t max_height) {
-  (void)params;
   if (max_gaussians < 1 || max_pairs < 1 || max_batches < 1 || max_width < 1 || max_height < 1)
     return HIGS_E_INVALID;
   higs_ctx c;
+  if (params) c.params = *params;
+  else higs_default_params(&c.params);
+  if (c.params.max_views < 1) return HIGS_E_INVALID;
   set_capacities(&c, max_gaussians, max_pairs, max_batches, max_width, max_height);
   int64_t bytes = 0;
   for_each_buffer(&c, [&](auto** ptr, size_t count) {
@@ -369,40 +408,54 @@ int higs_set_timing(higs_ctx* c, int n_frames) {
   return HIGS_OK;
 }
 
-int higs_project(higs_ctx* c, int64_t n, const float* means, const float* scales,
-                 const float* quats, const float* opacities, const float* sh,
-                 const higs_camera* cam, void* stream) {
-  if (!c || !cam || n < 0) return HIGS_E_INVALID;
-  if (n > 0 && (!means || !scales || !quats || !opacities || !sh)) return HIGS_E_INVALID;
-  if (cam->width < 1 || cam->height < 1) return HIGS_E_INVALID;
+}  // extern "C"
+
+namespace {
+// Camera fields of a view, and the frame's shared image geometry.
+void fill_view(ViewArgs& w, const higs_camera* cam) {
+  w.fx = cam->fx;
+  w.fy = cam->fy;
+  w.cx = cam->cx;
+  w.cy = cam->cy;
+  for (int r = 0; r < 3; ++r) {
+    for (int k = 0; k < 3; ++k) w.R[r * 3 + k] = cam->world_to_cam[r * 4 + k];
+    w.t[r] = cam->world_to_cam[r * 4 + 3];
+  }
+  for (int k = 0; k < 3; ++k) {
+    w.bg[k] = cam->background[k];
+    // camera centre -R^T t, for the SH view direction
+    w.campos[k] = -(w.R[k] * w.t[0] + w.R[3 + k] * w.t[1] + w.R[6 + k] * w.t[2]);
+  }
+}
+
+int check_camera(const higs_ctx* c, const higs_camera* cam) {
+  if (!cam || cam->width < 1 || cam->height < 1) return HIGS_E_INVALID;
   if (!(cam->fx > 0.0f) || !(cam->fy > 0.0f)) return HIGS_E_INVALID;
-  if (n > c->max_g || cam->width > c->max_w || cam->height > c->max_h) return HIGS_E_CAPACITY;
-  DeviceGuard g(c->device);
-  hipStream_t s = (hipStream_t)stream;
+  if (cam->width > c->max_w || cam->height > c->max_h) return HIGS_E_CAPACITY;
+  return HIGS_OK;
+}
+
+// Stage 1 for the frame's views (set in c->views): shared geometry, counters,
+// the projection of every view in one launch.
+int project_frame(higs_ctx* c, const higs_camera* cam0, hipStream_t s) {
   c->last_stream = s;
   c->stage = 0;
   if (c->timing()) c->frames += 1;
-  c->cam = *cam;
-  c->in_means = means;
-  c->in_scales = scales;
-  c->in_quats = quats;
-  c->in_opac = opacities;
-  c->in_sh = sh;
-  c->n = n;
+  c->cam = *cam0;
   CamArgs& a = c->ca;
-  a.width = cam->width;
-  a.height = cam->height;
-  a.n_mt_x = (cam->width + kMtW - 1) / kMtW;
-  a.n_mt_y = (cam->height + kMtH - 1) / kMtH;
-  a.fx = cam->fx;
-  a.fy = cam->fy;
-  a.cx = cam->cx;
-  a.cy = cam->cy;
+  a.width = cam0->width;
+  a.height = cam0->height;
+  a.n_mt_x = (cam0->width + kMtW - 1) / kMtW;
+  a.n_mt_y = (cam0->height + kMtH - 1) / kMtH;
+  a.fx = cam0->fx;
+  a.fy = cam0->fy;
+  a.cx = cam0->cx;
+  a.cy = cam0->cy;
   for (int r = 0; r < 3; ++r) {
-    for (int k = 0; k < 3; ++k) a.R[r * 3 + k] = cam->world_to_cam[r * 4 + k];
-    a.t[r] = cam->world_to_cam[r * 4 + 3];
+    for (int k = 0; k < 3; ++k) a.R[r * 3 + k] = cam0->world_to_cam[r * 4 + k];
+    a.t[r] = cam0->world_to_cam[r * 4 + 3];
   }
-  for (int k = 0; k < 3; ++k) a.bg[k] = cam->background[k];
+  for (int k = 0; k < 3; ++k) a.bg[k] = cam0->background[k];
   c->pa.alpha_max = c->params.alpha_max;
   c->pa.t_eps = c->params.t_eps;
   c->pa.near_z = c->params.near_z;
@@ -410,22 +463,64 @@ int higs_project(higs_ctx* c, int64_t n, const float* means, const float* scales
   c->pa.batch_cap = c->params.batch_cap;
   c->pa.sh_degree = c->params.sh_degree;
   c->n_mt = a.n_mt_x * a.n_mt_y;
-  c->n_passes = (32 + n_bits((uint32_t)(c->n_mt - 1)) + kRadixBits - 1) / kRadixBits;
+  c->n_mt_all = c->n_mt * c->n_views;
+  c->views.n_mt = c->n_mt;
+  c->views.n_pad = c->n_pad;
+  c->n_virt = c->n_pad * c->n_views;
+  c->n_passes = (32 + n_bits((uint32_t)(c->n_mt_all - 1)) + kRadixBits - 1) / kRadixBits;
   int rc = hip_err(launch_clear(c->dc, c->hist, kMaxPasses * kRadix, c->seg_count,
                                 c->segmented() ? c->n_mt : 0, s));
   if (rc) return rc;
   {
     TimerScope ts(c, HIGS_TIMER_PROJECT, s);
-    rc = hip_err(launch_project(n, means, scales, quats, opacities, sh, c->ca, c->pa, c->f_mx,
-                                c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau, c->f_key, c->f_cnt,
-                                c->f_span, c->rec, c->block_sums, c->dc,
-                                (c->debug_flags & HIGS_DEBUG_PROJ_FIELDS) != 0,
+    rc = hip_err(launch_project(c->views, c->ca, c->pa, c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c,
+                                c->f_tau, c->f_key, c->f_cnt, c->f_span, c->rec, c->block_sums,
+                                c->dc, (c->debug_flags & HIGS_DEBUG_PROJ_FIELDS) != 0,
                                 c->params.sh_format == HIGS_SH_PACKED32, s));
   }
   if (rc) return rc;
   c->stage = 1;
   return HIGS_OK;
 }
+
+
+}  // namespace
+
+extern "C" {
+
+int higs_project(higs_ctx* c, int64_t n, const float* means, const float* scales,
+                 const float* quats, const float* opacities, const float* sh,
+                 const higs_camera* cam, void* stream) {
+  if (!c || !cam || n < 0) return HIGS_E_INVALID;
+  if (n > 0 && (!means || !scales || !quats || !opacities || !sh)) return HIGS_E_INVALID;
+  int rc = check_camera(c, cam);
+  if (rc) return rc;
+  if (n > c->max_g) return HIGS_E_CAPACITY;
+  DeviceGuard g(c->device);
+  c->in_means = means;
+  c->in_scales = scales;
+  c->in_quats = quats;
+  c->in_opac = opacities;
+  c->in_sh = sh;
+  c->n = n;
+  c->n_views = 1;
+  c->n_pad = pad_blocks(n);
+  ViewArgs& w = c->views.v0;
+  w.means = means;
+  w.scales = scales;
+  w.quats = quats;
+  w.opac = opacities;
+  w.sh = sh;
+  w.n = n;
+  w.image = nullptr;
+  w.T = nullptr;
+  fill_view(w, cam);
+  c->views.count = 1;
+  c->views.table = nullptr;
+  return project_frame(c, cam, (hipStream_t)stream);
+}
+
+}  // extern "C"
 
 namespace {
 SegBuffers seg_buffers(higs_ctx* c) {
@@ -451,6 +546,8 @@ int keep_pairs(higs_ctx* c, hipStream_t s) {
   return rc;
 }
 }  // namespace
+
+extern "C" {
 
 int higs_bin_sort(higs_ctx* c, void* stream) {
   if (!c) return HIGS_E_INVALID;
@@ -487,14 +584,15 @@ int higs_bin_sort(higs_ctx* c, void* stream) {
   }
   {
     TimerScope ts(c, HIGS_TIMER_SCAN, s);
-    rc = hip_err(launch_scan(c->n > 0 ? c->n : 0, c->f_cnt, c->block_sums,
-                             (uint32_t)c->max_pairs, n_bits((uint32_t)(c->n_mt - 1)),
+    rc = hip_err(launch_scan(c->n_virt, c->f_cnt, c->block_sums,
+                             (uint32_t)c->max_pairs, n_bits((uint32_t)(c->n_mt_all - 1)),
                              (c->debug_flags & HIGS_DEBUG_TWO_WORD_PAIRS) == 0, c->dc, s));
   }
   if (rc) return rc;
   {
     TimerScope ts(c, HIGS_TIMER_FILL, s);
-    rc = hip_err(launch_fill(c->n, c->ca, c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau,
+    rc = hip_err(launch_fill(c->n_virt, c->ca, c->n_pad, (uint32_t)c->n_mt, c->f_mx, c->f_my,
+                             c->f_a, c->f_b, c->f_c, c->f_tau,
                              c->f_key, c->f_cnt, c->f_span, c->block_sums,
                              (uint32_t)c->max_pairs, c->dc, c->keys[0], c->vals[0], s));
   }
@@ -512,7 +610,7 @@ int higs_bin_sort(higs_ctx* c, void* stream) {
   sb.max_tiles = c->max_tiles;
   {
     TimerScope ts(c, HIGS_TIMER_SORT, s);
-    rc = hip_err(launch_sort(c->n_passes, n_bits((uint32_t)(c->n_mt - 1)), c->epoch, sb, c->dc,
+    rc = hip_err(launch_sort(c->n_passes, n_bits((uint32_t)(c->n_mt_all - 1)), c->epoch, sb, c->dc,
                              c->n_cus, s));
   }
   c->epoch += (uint32_t)c->n_passes;
@@ -544,7 +642,7 @@ int higs_batch(higs_ctx* c, void* stream) {
                                              (uint32_t)c->max_batches, c->dc, c->mt_off,
                                              c->batch_first, c->batch_tab, s));
     else
-      rc = hip_err(launch_batch(c->n_mt, (uint32_t)c->params.batch_cap, (uint32_t)c->max_batches,
+      rc = hip_err(launch_batch(c->n_mt_all, (uint32_t)c->params.batch_cap, (uint32_t)c->max_batches,
                                 k2, c->dc, c->mt_off, c->batch_first, c->batch_tab, s));
   }
   if (rc) return rc;
@@ -552,11 +650,11 @@ int higs_batch(higs_ctx* c, void* stream) {
   return HIGS_OK;
 }
 
-int higs_raster(higs_ctx* c, float* image, float* T_out, void* stream) {
-  if (!c || !image) return HIGS_E_INVALID;
-  if (c->stage < 3) return HIGS_E_STATE;
-  DeviceGuard g(c->device);
-  hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+namespace {
+// Stage 4 for the frame's views (their images are in c->views).
+int raster_frame(higs_ctx* c, hipStream_t s) {
   c->last_stream = s;
   const uint32_t* v2[2] = {c->vals[0], c->vals[1]};
   int rc;
@@ -575,15 +673,27 @@ int higs_raster(higs_ctx* c, float* image, float* T_out, void* stream) {
   {
     TimerScope ts(c, HIGS_TIMER_MERGE, s);
     if (half)
-      rc = hip_err(launch_merge16(c->ca, c->pa, c->batch_first, c->active, c->partials, c->dc,
-                                  image, T_out, s));
+      rc = hip_err(launch_merge16(c->ca, c->pa, c->views, c->batch_first, c->active, c->partials,
+                                  c->dc, s));
     else
-      rc = hip_err(launch_merge(c->ca, c->pa, c->batch_first, c->active, c->partials, c->dc,
-                                image, T_out, s));
+      rc = hip_err(launch_merge(c->ca, c->pa, c->views, c->batch_first, c->active, c->partials,
+                                c->dc, s));
   }
   if (rc) return rc;
   c->stage = 4;
   return HIGS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int higs_raster(higs_ctx* c, float* image, float* T_out, void* stream) {
+  if (!c || !image) return HIGS_E_INVALID;
+  if (c->stage < 3 || c->n_views != 1) return HIGS_E_STATE;
+  DeviceGuard g(c->device);
+  c->views.v0.image = image;
+  c->views.v0.T = T_out;
+  return raster_frame(c, (hipStream_t)stream);
 }
 
 int higs_render(higs_ctx* c, int64_t n, const float* means, const float* scales,
@@ -599,13 +709,81 @@ int higs_render(higs_ctx* c, int64_t n, const float* means, const float* scales,
   return higs_raster(c, image, T_out, stream);
 }
 
+int higs_render_views(higs_ctx* c, int32_t n_views, const higs_view* views, void* stream) {
+  if (!c || !views || n_views < 1) return HIGS_E_INVALID;
+  if (n_views > c->params.max_views) return HIGS_E_CAPACITY;
+  const higs_camera* cam0 = &views[0].camera;
+  int64_t n_max = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const higs_view& w = views[v];
+    if (w.n < 0 || !w.image) return HIGS_E_INVALID;
+    if (w.n > 0 && (!w.means || !w.scales || !w.quats || !w.opacities || !w.sh))
+      return HIGS_E_INVALID;
+    const int rc = check_camera(c, &w.camera);
+    if (rc) return rc;
+    if (w.camera.width != cam0->width || w.camera.height != cam0->height) return HIGS_E_INVALID;
+    if (w.n > c->max_g) return HIGS_E_CAPACITY;
+    n_max = w.n > n_max ? w.n : n_max;
+  }
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  c->n = views[0].n;
+  c->in_means = views[0].means;
+  c->in_scales = views[0].scales;
+  c->in_quats = views[0].quats;
+  c->in_opac = views[0].opacities;
+  c->in_sh = views[0].sh;
+  c->n_views = n_views;
+  c->n_pad = pad_blocks(n_max);
+  ViewArgs* slot = nullptr;
+  if (n_views > 1) {
+    // the view table goes to the device from a pinned slot that no earlier
+    // frame's copy still reads
+    const int k = c->view_slot;
+    c->view_slot = (c->view_slot + 1) % kViewRing;
+    if (hipEventSynchronize(c->view_ev[k]) != hipSuccess) return HIGS_E_HIP;
+    slot = c->view_stage + (size_t)k * c->params.max_views;
+  }
+  for (int v = 0; v < n_views; ++v) {
+    const higs_view& w = views[v];
+    ViewArgs a{};
+    a.means = w.means;
+    a.scales = w.scales;
+    a.quats = w.quats;
+    a.opac = w.opacities;
+    a.sh = w.sh;
+    a.n = w.n;
+    a.image = w.image;
+    a.T = w.T_out;
+    fill_view(a, &w.camera);
+    if (v == 0) c->views.v0 = a;
+    if (slot) slot[v] = a;
+  }
+  c->views.count = n_views;
+  c->views.table = n_views > 1 ? c->view_table : nullptr;
+  if (slot) {
+    const int k = (c->view_slot + kViewRing - 1) % kViewRing;
+    int rc = hip_err(hipMemcpyAsync(c->view_table, slot, sizeof(ViewArgs) * (size_t)n_views,
+                                    hipMemcpyHostToDevice, s));
+    if (!rc) rc = hip_err(hipEventRecord(c->view_ev[k], s));
+    if (rc) return rc;
+  }
+  int rc = project_frame(c, cam0, s);
+  if (rc) return rc;
+  rc = higs_bin_sort(c, stream);
+  if (rc) return rc;
+  rc = higs_batch(c, stream);
+  if (rc) return rc;
+  return raster_frame(c, s);
+}
+
 int higs_raster_backward(higs_ctx* c, const float* dL_dimage, const float* dL_dT, float* dmeans,
                          float* dscales, float* dquats, float* dopacities, float* dsh,
                          void* stream) {
   if (!c || !dL_dimage) return HIGS_E_INVALID;
   if (c->n > 0 && (!dmeans || !dscales || !dquats || !dopacities || !dsh)) return HIGS_E_INVALID;
   if (c->stage < 4) return HIGS_E_STATE;
-  if (c->params.raster_precision != HIGS_RASTER_FP32) return HIGS_E_UNSUPPORTED;
+  if (c->params.raster_precision != HIGS_RASTER_FP32 || c->n_views != 1) return HIGS_E_UNSUPPORTED;
   DeviceGuard g(c->device);
   if (!c->bwd_state) {
     if (dalloc(&c->bwd_state, (size_t)c->max_batches * kTilesPerMt * 64) != HIGS_OK ||
@@ -754,7 +932,7 @@ int higs_debug_copy(higs_ctx* c, int which, void* host_dst, size_t bytes) {
       return HIGS_OK;
     }
     case HIGS_DBG_MT_OFFSETS:
-      if (c->stage < 3 || bytes > ((size_t)c->n_mt + 1) * 4) return HIGS_E_INVALID;
+      if (c->stage < 3 || bytes > ((size_t)c->n_mt_all + 1) * 4) return HIGS_E_INVALID;
       return cp(c->mt_off, bytes);
     case HIGS_DBG_BATCHES:
       if (c->stage < 3 || bytes > nb * 12) return HIGS_E_INVALID;

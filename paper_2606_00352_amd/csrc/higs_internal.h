@@ -19,6 +19,7 @@ constexpr int kTilesPerMt = kMtTilesX * kMtTilesY;  // 32
 constexpr int kMaxBatch = 1024;  // largest B_r the rasteriser's LDS holds
 
 constexpr int kProjBlock = 256;  // gaussians per projection / emission block
+constexpr int kFillGroup = 4;    // projection blocks per emission workgroup
 // Projection blocks per scan chunk: a reduction writes each chunk's totals
 // after the n_blocks block sums, the scan runs over the chunk totals, and a
 // fill workgroup scans its chunk's block sums itself.
@@ -110,21 +111,54 @@ struct ParamArgs {
   int32_t batch_cap, sh_degree;
 };
 
+// A frame of several views (cameras of one image size, each with its own
+// scene arrays and image): view v owns the virtual gaussians
+// [v * n_pad, v * n_pad + n_v) and the macro-tiles [v * n_mt, (v + 1) * n_mt),
+// so that one launch of every stage serves all views: the pair keys carry the
+// view in their macro-tile field, and the sort, the batch split and the
+// rasteriser run unchanged over the concatenated macro-tile space.  A
+// single-view frame is the case V = 1 (n_pad = the gaussian count rounded up
+// to whole projection blocks).
+struct ViewArgs {
+  const float *means, *scales, *quats, *opac, *sh;
+  int64_t n;
+  float fx, fy, cx, cy;
+  float R[9];
+  float t[3];
+  float bg[3];
+  float campos[3];  // camera centre -R^T t (SH view directions)
+  float* image;
+  float* T;
+};
+
+// The views of a frame: the first by value (every single-view frame), the
+// others from a device table (table[v] for v >= 1; null when V = 1).
+struct Views {
+  int32_t count;
+  int64_t n_pad;  // virtual gaussians per view: a multiple of kProjBlock * kFillGroup
+  int32_t n_mt;   // macro-tiles per view
+  ViewArgs v0;
+  const ViewArgs* table;
+  __host__ __device__ __forceinline__ const ViewArgs& get(int v) const {
+    return v == 0 ? v0 : table[v];
+  }
+};
+
 // ---- host-side launchers (one translation unit each) ----------------------
 hipError_t launch_clear(DeviceCounters* dc, uint32_t* hist, int n_hist, uint32_t* seg_count,
                         int n_seg, hipStream_t s);
 
-hipError_t launch_project(int64_t n, const float* means, const float* scales, const float* quats,
-                          const float* opac, const float* sh, CamArgs cam, ParamArgs prm,
-                          float* f_mx, float* f_my, float* f_a, float* f_b, float* f_c,
-                          float* f_tau, uint32_t* f_key, uint32_t* f_cnt, uint32_t* f_span,
-                          RasterRecord* rec, uint32_t* block_sums, DeviceCounters* dc,
-                          bool all_fields, bool sh_packed, hipStream_t s);
+hipError_t launch_project(const Views& views, CamArgs shape, ParamArgs prm, float* f_mx,
+                          float* f_my, float* f_a, float* f_b, float* f_c, float* f_tau,
+                          uint32_t* f_key, uint32_t* f_cnt, uint32_t* f_span, RasterRecord* rec,
+                          uint32_t* block_sums, DeviceCounters* dc, bool all_fields,
+                          bool sh_packed, hipStream_t s);
 
 hipError_t launch_scan(int64_t n, const uint32_t* cnt, uint32_t* block_sums, uint32_t max_pairs,
                        int mt_bits, bool allow_one_word, DeviceCounters* dc, hipStream_t s);
 
-hipError_t launch_fill(int64_t n, CamArgs cam, const float* f_mx, const float* f_my,
+hipError_t launch_fill(int64_t n, CamArgs cam, int64_t n_pad, uint32_t n_mt, const float* f_mx,
+                       const float* f_my,
                        const float* f_a, const float* f_b, const float* f_c, const float* f_tau,
                        const uint32_t* f_key, const uint32_t* f_cnt, const uint32_t* f_span,
                        const uint32_t* block_offsets, uint32_t max_pairs,
@@ -157,13 +191,13 @@ hipError_t launch_raster16(CamArgs cam, ParamArgs prm, const uint32_t* const* va
                            const RasterRecord* rec, const uint32_t* batch_tab, DeviceCounters* dc,
                            void* partials, uint32_t* active, int n_cus, bool count_evals,
                            hipStream_t s);
-hipError_t launch_merge16(CamArgs cam, ParamArgs prm, const uint32_t* batch_first,
-                          const uint32_t* active, const void* partials, const DeviceCounters* dc,
-                          float* image, float* T_out, hipStream_t s);
+hipError_t launch_merge16(CamArgs cam, ParamArgs prm, const Views& views,
+                          const uint32_t* batch_first, const uint32_t* active, const void* partials,
+                          const DeviceCounters* dc, hipStream_t s);
 
-hipError_t launch_merge(CamArgs cam, ParamArgs prm, const uint32_t* batch_first,
+hipError_t launch_merge(CamArgs cam, ParamArgs prm, const Views& views, const uint32_t* batch_first,
                         const uint32_t* active, const float4* partials, const DeviceCounters* dc,
-                        float* image, float* T_out, hipStream_t s);
+                        hipStream_t s);
 
 // Adjoint of the frame (clear, merge, raster and projection adjoints).
 // state: float2 per (batch, tile, pixel); dgeo: 16 floats per gaussian.

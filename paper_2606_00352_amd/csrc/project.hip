@@ -172,20 +172,42 @@ __device__ __forceinline__ float3 sh_colour(Co&& co, int degree, float x, float 
   return make_float3(fmaxf(0.0f, 0.5f + acc.x), fmaxf(0.0f, 0.5f + acc.y), fmaxf(0.0f, 0.5f + acc.z));
 }
 
+// A workgroup takes 256 gaussians of one view; the views of one range of
+// gaussians are neighbouring workgroups (workgroup w: view w mod V, block
+// w / V), so views of one scene find its arrays in the caches.  Every output
+// sits at the virtual index v * n_pad + i.
 __global__ void __launch_bounds__(kProjBlock)
-project_kernel(int64_t n, const float* __restrict__ means, const float* __restrict__ scales,
-               const float* __restrict__ quats, const float* __restrict__ opac,
-               const float* __restrict__ sh, CamArgs cam, ParamArgs prm, float3 campos,
-               float* __restrict__ f_mx, float* __restrict__ f_my, float* __restrict__ f_a,
-               float* __restrict__ f_b, float* __restrict__ f_c, float* __restrict__ f_tau,
-               uint32_t* __restrict__ f_key, uint32_t* __restrict__ f_cnt,
-               uint32_t* __restrict__ f_span, RasterRecord* __restrict__ rec,
-               uint32_t* __restrict__ block_sums, DeviceCounters* __restrict__ dc, bool sh_vec4,
-               bool all_fields, bool sh_packed) {
+project_kernel(Views views, CamArgs shape, ParamArgs prm, float* __restrict__ f_mx,
+               float* __restrict__ f_my, float* __restrict__ f_a, float* __restrict__ f_b,
+               float* __restrict__ f_c, float* __restrict__ f_tau, uint32_t* __restrict__ f_key,
+               uint32_t* __restrict__ f_cnt, uint32_t* __restrict__ f_span,
+               RasterRecord* __restrict__ rec, uint32_t* __restrict__ block_sums,
+               DeviceCounters* __restrict__ dc, bool all_fields, bool sh_packed) {
   __shared__ uint32_t wave_min[kProjBlock / 64], wave_max[kProjBlock / 64];
   __shared__ uint32_t wave_sums[2][kProjBlock / 64];
   __shared__ float sh_scale[kShComps];
-  const int64_t i = (int64_t)blockIdx.x * kProjBlock + threadIdx.x;
+  const int view = (int)(blockIdx.x % (uint32_t)views.count);
+  const int64_t blk = (int64_t)(blockIdx.x / (uint32_t)views.count);
+  const ViewArgs w = view == 0 ? views.v0 : views.table[view];
+  const float* __restrict__ means = w.means;
+  const float* __restrict__ scales = w.scales;
+  const float* __restrict__ quats = w.quats;
+  const float* __restrict__ opac = w.opac;
+  const float* __restrict__ sh = w.sh;
+  const int64_t n = w.n;
+  CamArgs cam = shape;
+  cam.fx = w.fx;
+  cam.fy = w.fy;
+  cam.cx = w.cx;
+  cam.cy = w.cy;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) cam.R[k] = w.R[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) cam.t[k] = w.t[k];
+  const float3 campos = make_float3(w.campos[0], w.campos[1], w.campos[2]);
+  const bool sh_vec4 = (reinterpret_cast<uintptr_t>(sh) & 15u) == 0;
+  const int64_t i = blk * kProjBlock + threadIdx.x;  // in the view
+  const int64_t vi = view * views.n_pad + i;           // virtual
   uint32_t cnt = 0;
   uint32_t kmin = 0xffffffffu, kmax = 0u;
   // degree 3 with a 16-byte aligned sh array: the 48 coefficients (192
@@ -232,16 +254,16 @@ project_kernel(int64_t n, const float* __restrict__ means, const float* __restri
       cnt = visit_macro_tiles_ji(f, cam.width, cam.height, cam.n_mt_x, cam.n_mt_y,
                                  [&](int j, int ic) { span.add(j, ic); });
       const uint32_t sw = cnt > 0 ? span.encode() : 0u;
-      if (cnt > 0) f_span[i] = sw;
+      if (cnt > 0) f_span[vi] = sw;
       // the binning fields: read again only for a list the span word cannot
       // hold (and by the debug read-back)
       if (all_fields || (cnt > 0 && sw == 0)) {
-        f_mx[i] = f.mx;
-        f_my[i] = f.my;
-        f_a[i] = f.a;
-        f_b[i] = f.b;
-        f_c[i] = f.c;
-        f_tau[i] = f.tau;
+        f_mx[vi] = f.mx;
+        f_my[vi] = f.my;
+        f_a[vi] = f.a;
+        f_b[vi] = f.b;
+        f_c[vi] = f.c;
+        f_tau[vi] = f.tau;
       }
       if (cnt > 0) {
         kmin = key;
@@ -280,14 +302,17 @@ project_kernel(int64_t n, const float* __restrict__ means, const float* __restri
         r.tau = f.tau;
         r.pad0 = 0.0f;
         r.pad1 = 0.0f;
-        float4* dst = reinterpret_cast<float4*>(rec + i);
+        float4* dst = reinterpret_cast<float4*>(rec + vi);
         dst[0] = make_float4(r.mx, r.my, r.l0, r.l1);
         dst[1] = make_float4(r.l2, r.o, r.r, r.g);
         dst[2] = make_float4(r.b, r.tau, 0.0f, 0.0f);
       }
     }
-    f_key[i] = key;
-    f_cnt[i] = cnt;
+    f_key[vi] = key;
+    f_cnt[vi] = cnt;
+  } else if (i < views.n_pad) {  // padding of the view's range
+    f_key[vi] = 0u;
+    f_cnt[vi] = 0u;
   }
   // block sums of the pair counts and visible gaussians (emission scan) and
   // the frame-wide range of the visible depth bits
@@ -314,8 +339,9 @@ project_kernel(int64_t n, const float* __restrict__ means, const float* __restri
       tp += wave_sums[0][w];
       tv += wave_sums[1][w];
     }
-    block_sums[2 * blockIdx.x] = tp;
-    block_sums[2 * blockIdx.x + 1] = tv;
+    const int64_t vb = view * (views.n_pad / kProjBlock) + blk;  // virtual block
+    block_sums[2 * vb] = tp;
+    block_sums[2 * vb + 1] = tv;
   }
   if (threadIdx.x == 0) {
 #pragma unroll
@@ -334,23 +360,16 @@ project_kernel(int64_t n, const float* __restrict__ means, const float* __restri
   }
 }
 
-hipError_t launch_project(int64_t n, const float* means, const float* scales, const float* quats,
-                          const float* opac, const float* sh, CamArgs cam, ParamArgs prm,
-                          float* f_mx, float* f_my, float* f_a, float* f_b, float* f_c,
-                          float* f_tau, uint32_t* f_key, uint32_t* f_cnt, uint32_t* f_span,
-                          RasterRecord* rec, uint32_t* block_sums, DeviceCounters* dc,
-                          bool all_fields, bool sh_packed, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  // camera centre, -R^T t, for the SH view direction
-  float3 campos;
-  campos.x = -(cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1] + cam.R[6] * cam.t[2]);
-  campos.y = -(cam.R[1] * cam.t[0] + cam.R[4] * cam.t[1] + cam.R[7] * cam.t[2]);
-  campos.z = -(cam.R[2] * cam.t[0] + cam.R[5] * cam.t[1] + cam.R[8] * cam.t[2]);
-  const unsigned blocks = (unsigned)((n + kProjBlock - 1) / kProjBlock);
-  hipLaunchKernelGGL(project_kernel, dim3(blocks), dim3(kProjBlock), 0, s, n, means, scales,
-                     quats, opac, sh, cam, prm, campos, f_mx, f_my,
-                     f_a, f_b, f_c, f_tau, f_key, f_cnt, f_span, rec, block_sums, dc,
-                     (reinterpret_cast<uintptr_t>(sh) & 15u) == 0, all_fields, sh_packed);
+hipError_t launch_project(const Views& views, CamArgs shape, ParamArgs prm, float* f_mx,
+                          float* f_my, float* f_a, float* f_b, float* f_c, float* f_tau,
+                          uint32_t* f_key, uint32_t* f_cnt, uint32_t* f_span, RasterRecord* rec,
+                          uint32_t* block_sums, DeviceCounters* dc, bool all_fields,
+                          bool sh_packed, hipStream_t s) {
+  if (views.n_pad <= 0 || views.count <= 0) return hipSuccess;
+  const int64_t blocks = (views.n_pad / kProjBlock) * views.count;
+  hipLaunchKernelGGL(project_kernel, dim3((unsigned)blocks), dim3(kProjBlock), 0, s, views, shape,
+                     prm, f_mx, f_my, f_a, f_b, f_c, f_tau, f_key, f_cnt, f_span, rec, block_sums,
+                     dc, all_fields, sh_packed);
   return hipGetLastError();
 }
 

@@ -97,17 +97,17 @@ raster_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ vals0,
 
 constexpr int kMergeThreads = 256;
 __global__ void __launch_bounds__(kMergeThreads)
-merge_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ batch_first,
+merge_kernel(CamArgs cam, ParamArgs prm, Views views, const uint32_t* __restrict__ batch_first,
              const uint32_t* __restrict__ active, const float4* __restrict__ partials,
-             const DeviceCounters* __restrict__ dc, float* __restrict__ image,
-             float* __restrict__ T_out) {
+             const DeviceCounters* __restrict__ dc) {
+  // grid: (tile columns / waves per block, tile rows, views); a wave per tile
   const int tiles_x = (cam.width + kTile - 1) / kTile;
-  const int tiles_y = (cam.height + kTile - 1) / kTile;
-  const int tile = blockIdx.x * (kMergeThreads / 64) + (threadIdx.x >> 6);
-  if (tile >= tiles_x * tiles_y) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int tx = (int)blockIdx.x * (kMergeThreads / 64) + wave, ty = (int)blockIdx.y;
+  const int view = (int)blockIdx.z;
+  if (tx >= tiles_x) return;
   const int lane = threadIdx.x & 63;
-  const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const uint32_t mt = (uint32_t)((ty / kMtTilesY) * cam.n_mt_x + tx / kMtTilesX);
+  const uint32_t mt = (uint32_t)(view * views.n_mt + (ty / kMtTilesY) * cam.n_mt_x + tx / kMtTilesX);
   const uint32_t t = (uint32_t)((ty % kMtTilesY) * kMtTilesX + tx % kMtTilesX);
   const uint32_t nb = dc->overflow ? 0u : dc->n_batches;
   const uint32_t b0 = min(batch_first[mt], nb), b1 = min(batch_first[mt + 1], nb);
@@ -154,10 +154,13 @@ merge_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ batch_firs
     cr = cg = cb = T = __builtin_nanf("");
   }
   if (x < cam.width && y < cam.height) {
+    const ViewArgs& w = view == 0 ? views.v0 : views.table[view];
+    float* __restrict__ image = w.image;
+    float* __restrict__ T_out = w.T;
     const size_t pix = (size_t)y * cam.width + x;
-    image[3 * pix + 0] = cr + T * cam.bg[0];
-    image[3 * pix + 1] = cg + T * cam.bg[1];
-    image[3 * pix + 2] = cb + T * cam.bg[2];
+    image[3 * pix + 0] = cr + T * w.bg[0];
+    image[3 * pix + 1] = cg + T * w.bg[1];
+    image[3 * pix + 2] = cb + T * w.bg[2];
     if (T_out) T_out[pix] = T;
   }
 }
@@ -185,14 +188,14 @@ hipError_t launch_raster(CamArgs cam, ParamArgs prm, const uint32_t* const* vals
   return hipGetLastError();
 }
 
-hipError_t launch_merge(CamArgs cam, ParamArgs prm, const uint32_t* batch_first,
+hipError_t launch_merge(CamArgs cam, ParamArgs prm, const Views& views, const uint32_t* batch_first,
                         const uint32_t* active, const float4* partials, const DeviceCounters* dc,
-                        float* image, float* T_out, hipStream_t s) {
-  const int tiles = ((cam.width + kTile - 1) / kTile) * ((cam.height + kTile - 1) / kTile);
-  const int blocks = (tiles + (kMergeThreads / 64) - 1) / (kMergeThreads / 64);
-  if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(merge_kernel, dim3(blocks), dim3(kMergeThreads), 0, s, cam, prm, batch_first,
-                     active, partials, dc, image, T_out);
+                        hipStream_t s) {
+  const int tiles_x = (cam.width + kTile - 1) / kTile, tiles_y = (cam.height + kTile - 1) / kTile;
+  const dim3 grid((tiles_x + kMergeThreads / 64 - 1) / (kMergeThreads / 64), tiles_y, views.count);
+  if (tiles_x == 0 || tiles_y == 0 || views.count == 0) return hipSuccess;
+  hipLaunchKernelGGL(merge_kernel, grid, dim3(kMergeThreads), 0, s, cam, prm, views,
+                     batch_first, active, partials, dc);
   return hipGetLastError();
 }
 

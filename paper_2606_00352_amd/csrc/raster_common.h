@@ -98,7 +98,10 @@ __device__ __forceinline__ UnitInfo unit_info(const CamArgs& cam, const uint32_t
   I.mt = batch_tab[3 * u + 0];
   I.start = batch_tab[3 * u + 1];
   I.len = (int)batch_tab[3 * u + 2];
-  const int mtx = (int)(I.mt % (uint32_t)cam.n_mt_x), mty = (int)(I.mt / (uint32_t)cam.n_mt_x);
+  // a frame of several views numbers the macro-tiles of view v after those of
+  // views 0 .. v-1: the position in the image is the local number's
+  const uint32_t mtl = I.mt % (uint32_t)(cam.n_mt_x * cam.n_mt_y);
+  const int mtx = (int)(mtl % (uint32_t)cam.n_mt_x), mty = (int)(mtl / (uint32_t)cam.n_mt_x);
   I.x0 = mtx * kMtW;
   I.y0 = mty * kMtH;
   I.tiles_x = min(kMtTilesX, (cam.width - I.x0 + kTile - 1) / kTile);

@@ -31,7 +31,7 @@ EXPORTS = ("higs_default_params", "higs_ctx_create", "higs_ctx_destroy", "higs_p
            "higs_error_string", "higs_raster_backward", "higs_ctx_footprint",
            "higs_server_create", "higs_server_destroy", "higs_server_add_scene", "higs_server_submit",
            "higs_server_poll", "higs_server_get_stats", "higs_render_noalloc", "higs_sh_packed_bytes",
-           "higs_sh_compress")
+           "higs_sh_compress", "higs_render_views")
 
 
 class HigsError(RuntimeError):
@@ -46,7 +46,8 @@ class Params(ctypes.Structure):
                 ("sh_degree", ctypes.c_int32), ("alpha_max", ctypes.c_float),
                 ("t_eps", ctypes.c_float), ("near_z", ctypes.c_float),
                 ("dilation", ctypes.c_float), ("sort_mode", ctypes.c_int32),
-                ("raster_precision", ctypes.c_int32), ("sh_format", ctypes.c_int32)]
+                ("raster_precision", ctypes.c_int32), ("sh_format", ctypes.c_int32),
+                ("max_views", ctypes.c_int32)]
 
 
 class CameraC(ctypes.Structure):
@@ -65,6 +66,13 @@ class Counts(ctypes.Structure):
 
 
 MAX_CLASSES = 4
+MAX_VIEWS = 64
+
+
+class ViewC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("means", ctypes.c_void_p), ("scales", ctypes.c_void_p),
+                ("quats", ctypes.c_void_p), ("opacities", ctypes.c_void_p), ("sh", ctypes.c_void_p),
+                ("camera", CameraC), ("image", ctypes.c_void_p), ("T_out", ctypes.c_void_p)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -121,6 +129,7 @@ def lib():
             "higs_render_noalloc": (ctypes.c_int, [i64, P, P, P, P, P, P, P, P, P]),
             "higs_sh_packed_bytes": (i64, [i64]),
             "higs_sh_compress": (ctypes.c_int, [i64, P, P, P, P]),
+            "higs_render_views": (ctypes.c_int, [P, i32, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -208,7 +217,7 @@ class Context:
         self.grown = 0  # times render_checked grew the context
 
     def _batches_for(self, max_pairs, max_width, max_height):
-        n_mt = ((max_width + 63) // 64) * ((max_height + 31) // 32)
+        n_mt = ((max_width + 63) // 64) * ((max_height + 31) // 32) * max(1, self.params.max_views)
         return max_pairs // max(1, self.params.batch_cap) + n_mt + 16
 
     def _create(self):
@@ -288,6 +297,26 @@ class Context:
             want_b = int(c.n_batches * 1.25) + 64 if c.overflow & OVF_BATCHES else 0
             self.grow(want_p, want_b)
         raise CapacityError(c)
+
+    def render_views(self, views, stream=None):
+        """higs_render_views: views = [(tensors (means, scales, quats, opacities,
+        sh), camera, image [H,W,3], T [H,W] or None), ...], all cameras of one
+        size; one launch per kernel for all of them."""
+        arr = (ViewC * len(views))()
+        for k, (tens, cam, image, T) in enumerate(views):
+            means, scales, quats, opac, sh = tens
+            v = arr[k]
+            v.n = int(means.shape[0])
+            v.means, v.scales, v.quats = _ptr(means), _ptr(scales), _ptr(quats)
+            v.opacities, v.sh = _ptr(opac), _ptr(sh)
+            v.camera = camera_c(cam)
+            v.image, v.T_out = _ptr(image), _ptr(T)
+        if views:
+            self.frame_id += 1
+            cam0 = views[0][1]
+            self.n = int(views[0][0][0].shape[0])
+            self.n_mt = ((cam0.width + 63) // 64) * ((cam0.height + 31) // 32) * len(views)
+        _check(lib().higs_render_views(self._h, len(views), arr, _stream(stream)), "higs_render_views")
 
     def raster_backward(self, d_image, d_T, d_means, d_scales, d_quats, d_opacities, d_sh, stream=None):
         """Adjoint of the last frame (higs_raster_backward): writes the gradient

@@ -100,7 +100,8 @@ int main(int argc, char** argv) {
   }
   fclose(jf);
   const int debug_flags = getenv("HIGS_CPU_DEBUG") ? atoi(getenv("HIGS_CPU_DEBUG")) : 0;
-  if (entry == 0) {
+  if (entry == 2) p.max_views = (int)cams.size();
+  if (entry == 0 || entry == 2) {
     const int rc = higs_ctx_create(0, &p, n, max_pairs, max_batches, max_w, max_h, &ctx);
     if (rc) {
       fprintf(stderr, "higs_ctx_create: %d\n", rc);
@@ -109,6 +110,43 @@ int main(int argc, char** argv) {
     if (debug_flags && higs_set_debug(ctx, debug_flags)) return 3;
   }
   FILE* summary = fopen((out + "/counts.txt").c_str(), "w");
+  if (entry == 2) {  // every frame of the job as one view of a single frame
+    std::vector<higs_view> vs(cams.size());
+    std::vector<float*> bufs;
+    for (size_t f = 0; f < cams.size(); ++f) {
+      const size_t npx = (size_t)cams[f].width * cams[f].height;
+      float* b = static_cast<float*>(mmap(nullptr, npx * 16, PROT_READ | PROT_WRITE,
+                                         MAP_SHARED | MAP_ANONYMOUS, -1, 0));
+      if (b == MAP_FAILED) return 2;
+      for (size_t q = 0; q < npx * 4; ++q) b[q] = -7.0f;
+      bufs.push_back(b);
+      higs_view& v = vs[f];
+      v.n = uses[f];
+      v.means = means.data();
+      v.scales = scales.data();
+      v.quats = quats.data();
+      v.opacities = opac.data();
+      v.sh = sh_in;
+      v.camera = cams[f];
+      v.image = b;
+      v.T_out = b + npx * 3;
+    }
+    const int rc = higs_render_views(ctx, (int32_t)vs.size(), vs.data(), nullptr);
+    higs_counts cn{};
+    if (!rc && higs_get_counts(ctx, &cn)) return 4;
+    for (size_t f = 0; f < cams.size(); ++f) {
+      const size_t npx = (size_t)cams[f].width * cams[f].height;
+      const std::string pre = out + "/f" + std::to_string(f) + "_";
+      save(pre + "image", bufs[f], npx * 12);
+      save(pre + "T", bufs[f] + npx * 3, npx * 4);
+      fprintf(summary, "%d %lld %lld %lld %lld %u\n", rc, (long long)cn.n_visible,
+              (long long)cn.n_pairs, (long long)cn.n_batches, (long long)cn.n_evaluations,
+              cn.overflow);
+    }
+    fclose(summary);
+    higs_ctx_destroy(ctx);
+    return 0;
+  }
   for (size_t f = 0; f < cams.size(); ++f) {
     const higs_camera& c = cams[f];
     const size_t npx = (size_t)c.width * c.height;

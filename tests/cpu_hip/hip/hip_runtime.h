@@ -505,6 +505,7 @@ enum hipMemcpyKind {
 #define hipStreamNonBlocking 1
 #define hipStreamDefault 0
 #define hipHostMallocDefault 0
+#define hipEventDisableTiming 2
 struct hipDeviceProp_t {
   char name[256];
   int multiProcessorCount;

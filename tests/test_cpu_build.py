@@ -98,3 +98,23 @@ def test_half_precision_raster(orc):
     assert np.array_equal(fr.batches.astype(np.int64), o.batch_tab.astype(np.int64))
     assert _psnr(fr.image, o.image) >= 55.0
     assert np.all(np.isfinite(fr.image)) and np.all((fr.T >= 0) & (fr.T <= 1))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_views_in_one_frame_match_their_single_frames(precision):
+    """higs_render_views: three views (different cameras, two scene sizes)
+    rendered as one frame give, view by view, the images and transmittances
+    of three single-view frames, bit for bit; the frame's pairs are the sum
+    of the single frames' pairs."""
+    cpu = _cpu()
+    sc = scenes.clustered_scene(6000, seed=6, n_clusters=4)
+    cams = scenes.orbit_cameras(5, 3, 160, 96, 140.0)[:3]
+    uses = [6000, 4000, 6000]
+    single = cpu.run_frames(sc, cams, max_pairs=1 << 17, max_batches=1 << 12, uses=uses,
+                            precision=precision)
+    multi = cpu.run_frames(sc, cams, max_pairs=1 << 17, max_batches=1 << 12, uses=uses, entry=2,
+                           precision=precision)
+    assert all(f.rc == 0 and f.overflow == 0 for f in single + multi)
+    assert multi[0].n_pairs == sum(f.n_pairs for f in single)
+    for a, b in zip(single, multi):
+        assert np.array_equal(a.image, b.image) and np.array_equal(a.T, b.T)

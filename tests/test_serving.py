@@ -17,7 +17,8 @@ from paper_2606_00352_amd import higs, scenes
 def test_context_footprint_counts_every_array():
     G, P, B, W, H = 1000, 5000, 40, 200, 100
     n_mt = ((W + 63) // 64) * ((H + 31) // 32)
-    nblk = (G + 255) // 256
+    G = (G + 1023) // 1024 * 1024         # per-gaussian arrays: whole groups of four 256-blocks
+    nblk = G // 256
     tiles = (P + 6143) // 6144
     radix = 512                           # 9-bit sort digits
     nchunk = (nblk + 255) // 256          # scan chunks of 256 projection blocks
@@ -25,10 +26,14 @@ def test_context_footprint_counts_every_array():
             + tiles * radix * 8
             + 2 * (n_mt + 1) * 4 + B * 16 + B * 32 * 64 * 16)
     got = higs.ctx_footprint(G, P, B, W, H)
-    assert 0 < got - want <= 512          # plus the frame counters
+    assert 0 < got - want <= 1024         # plus the frame counters and the view table
     assert higs.ctx_footprint(G, 2 * P, B, W, H) > got
     assert higs.ctx_footprint(G, P, 2 * B, W, H) - got == B * (16 + 32 * 64 * 16)
     assert higs.ctx_footprint(0, P, B, W, H) == higs.E_INVALID
+    # four views per frame: four ranges of gaussians and of macro-tiles
+    four = higs.ctx_footprint(G, P, B, W, H, max_views=4)
+    grow = 3 * (G * (9 * 4 + 48) + 2 * nblk * 4 + 6 * n_mt * 4)
+    assert 0 < four - got - grow <= 3 * 256
 
 
 def test_serving_trace_is_poisson_and_uniform():
