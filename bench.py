@@ -203,16 +203,21 @@ def backward_leg(n=1_000_000, warmup=5, steps=20):
     return res
 
 
-def serving_leg(warm=1.0, measured=4.0, drain=6.0, rate=2000.0, budget_gb=96.0, max_in_flight=16):
+def serving_leg(window=10.0, warm=1.0, drain=4.0, load=0.7, budget_gb=96.0, max_in_flight=16,
+                tune_frames=24):
     """The serving workload: four resident clustered scenes (0.5M, 1.5M, 3M,
-    5.8M gaussians), Poisson requests at `rate`/s for warm + measured seconds,
-    each a random orbit camera at 720p, 1080p or 4K.  Requests are replayed in
-    real time against the server (continuous batching, max_in_flight frames at
-    once) and against the plain renderer (the same server with one frame at a
-    time), each allowed `drain` seconds after the last arrival.  Latency =
-    completion seen by the host - arrival; served frames/s = completions
-    within the measured window / its length; percentiles over the requests
-    that arrived in the measured window (unfinished ones are counted)."""
+    5.8M gaussians); each request picks a scene and a resolution (720p, 1080p,
+    4K) uniformly and a random orbit camera.  Two servers: the batched one
+    (max_in_flight frames at once, views per frame per class chosen by the
+    server's autotuner on the 5.8M scene, frames replayed from HIP graphs)
+    and the plain renderer (one frame at a time, one request per frame,
+    kernel by kernel).  For each: saturation throughput (closed loop: a new
+    request as soon as an image buffer is free; completions in a `window`-s
+    window after `warm` s), then latency at `load` x that throughput (Poisson
+    arrivals replayed in real time for warm + window s; p50/p99 of completion
+    seen by the host - arrival, over the requests that arrived in the window,
+    unfinished ones counted as infinite).  A sample of served images is
+    compared with the same requests rendered alone (bit for bit)."""
     import collections
     import numpy as np
     import torch
@@ -222,64 +227,120 @@ def serving_leg(warm=1.0, measured=4.0, drain=6.0, rate=2000.0, budget_gb=96.0, 
     tens = [higs.scene_tensors(x, "cuda:0") for x in sc]
     nmax = max(x.n for x in sc)
     del sc
-    trace = scenes.serving_trace(warm + measured, rate)
-    log(f"serving: scenes ready in {time.perf_counter() - t:.1f} s, {len(trace)} requests")
     res = scenes.SERVING_RESOLUTIONS
     classes = [(w, h, int(k * nmax)) for (w, h), k in zip(res, (1.5, 2.5, 4.5))]
+    pool_req = scenes.serving_trace(60.0, rate=2000.0, seed=36)   # cameras / scenes to draw from
+    log(f"serving: scenes ready in {time.perf_counter() - t:.1f} s")
 
-    def run(mif):
-        srv = higs.Server(classes, max_gaussians=nmax, hbm_budget=int(budget_gb * 2**30), max_in_flight=mif)
+    def make(batched):
+        srv = higs.Server(classes, max_gaussians=nmax, hbm_budget=int(budget_gb * 2**30),
+                          max_in_flight=max_in_flight if batched else 1, use_graphs=batched)
         for k, tt in enumerate(tens):
             srv.add_scene(k, tt)
-        pool = {c: [torch.empty((h, w, 3), device="cuda:0") for _ in range(2 * mif)]
-                for c, (w, h) in enumerate(res)}
-        holding, lat, done_at, gpu_ms = {}, {}, {}, []
-        pending = collections.deque()
-        overflow = 0
-        nxt = 0
+        tuned = None
+        if batched:
+            tuned = []
+            for c, (w, h) in enumerate(res):
+                cams = [r.camera for r in pool_req if r.cls == c][:16]
+                rep = srv.tune(c, 3, cams, frames=tune_frames)
+                tuned.append({"class": f"{w}x{h}", "views_per_frame": rep.views_per_frame,
+                              "trials_fps": {int(rep.trial_views[i]): round(float(rep.trial_fps[i]), 1)
+                                             for i in range(rep.n_trials)}})
+                log(f"serving: tuned {w}x{h}: {tuned[-1]}")
+        return srv, tuned
+
+    def drive(srv, reqs, realtime, t_end, nbuf, keep=()):
+        """Submits reqs (in real time at their arrival, or as soon as a buffer
+        is free); returns completion times, latencies, device times and the
+        images of the request ids in keep."""
+        pool = {c: [torch.empty((h, w, 3), device="cuda:0") for _ in range(nbuf)] for c, (w, h) in enumerate(res)}
+        holding, done_at, lat, gpu_ms, kept = {}, {}, {}, [], {}
+        pending = [collections.deque() for _ in res]   # arrived, waiting for an image buffer
+        nxt, overflow = 0, 0
         t0 = time.perf_counter()
-        end = trace[-1].arrival + drain
-        while len(lat) < len(trace):
+        while True:
             now = time.perf_counter() - t0
-            if now > end:
+            if now > t_end or (nxt == len(reqs) and not any(pending) and not holding):
                 break
-            while nxt < len(trace) and trace[nxt].arrival <= now:
-                pending.append(trace[nxt])
+            # arrivals (closed loop: the next request as soon as its class has a buffer)
+            while nxt < len(reqs) and (reqs[nxt].arrival <= now if realtime else pool[reqs[nxt].cls]):
+                pending[reqs[nxt].cls].append((reqs[nxt], reqs[nxt].arrival if realtime else now))
                 nxt += 1
-            kept = collections.deque()
-            while pending:
-                r = pending.popleft()
-                if pool[r.cls]:
-                    buf = pool[r.cls].pop()
-                    holding[r.id] = (r.cls, buf)
+                if not realtime:
+                    break
+            for c, q in enumerate(pending):
+                while q and pool[c]:
+                    r, arr = q.popleft()
+                    buf = pool[c].pop()
+                    holding[r.id] = (c, buf, arr)
                     srv.submit(r.id, r.scene, r.cls, r.camera, buf)
-                else:
-                    kept.append(r)
-            pending = kept
             for rid, ms, ovf, cls in srv.poll():
-                tdone = time.perf_counter() - t0
-                lat[rid] = tdone - trace[rid].arrival
-                done_at[rid] = tdone
+                td = time.perf_counter() - t0
+                c, buf, arr = holding.pop(rid)
+                done_at[rid] = td
+                lat[rid] = td - arr
                 gpu_ms.append(ms)
                 overflow += ovf != 0
-                c, buf = holding.pop(rid)
+                if rid in keep:
+                    kept[rid] = buf.clone()
                 pool[c].append(buf)
+        # what is still queued or rendering finishes before the next run
+        # (not counted)
+        t1 = time.perf_counter()
+        while holding and time.perf_counter() - t1 < 60.0:
+            for rid, ms, ovf, cls in srv.poll():
+                holding.pop(rid, None)
         torch.cuda.synchronize()
+        return done_at, lat, gpu_ms, overflow, kept
+
+    def saturation(srv, nbuf):
+        reqs = [scenes.Request(i, 0.0, r.scene, r.cls, r.camera) for i, r in enumerate(pool_req)]
+        done_at, _, gpu_ms, ovf, _ = drive(srv, reqs, False, warm + window, nbuf)
+        n = sum(1 for d in done_at.values() if warm <= d < warm + window)
+        return n / window, ovf
+
+    def latency(srv, rate, nbuf, keep=()):
+        tr = scenes.serving_trace(warm + window, rate=rate, seed=37)
+        done_at, lat, gpu_ms, ovf, kept = drive(srv, tr, True, warm + window + drain, nbuf, keep)
+        in_win = [r.id for r in tr if r.arrival >= warm]
+        l = np.array([lat.get(i, np.inf) for i in in_win])
+        served = sum(1 for d in done_at.values() if warm <= d < warm + window) / window
+        pct = lambda q: (round(float(np.percentile(l, q)) * 1e3, 2) if np.isfinite(np.percentile(l, q)) else None)
+        return {"rate": round(rate, 1), "served_fps": round(served, 1), "p50_ms": pct(50), "p99_ms": pct(99),
+                "unfinished_in_window": int(np.isinf(l).sum()), "requests": len(tr),
+                "mean_gpu_ms": round(float(np.mean(gpu_ms)), 4) if gpu_ms else None,
+                "overflow_frames": ovf}, tr, kept
+
+    out = {"workload": "4 resident scenes (0.5M/1.5M/3M/5.8M), uniform over 720p/1080p/4K, random orbit cameras; "
+                       f"saturation = closed loop over a {window:.0f} s window, latency at {load:.0%} of it "
+                       f"(Poisson, {window:.0f} s window)", "max_in_flight": max_in_flight}
+    for name, batched in (("batched", True), ("plain", False)):
+        srv, tuned = make(batched)
+        nbuf = 4 * max_in_flight if batched else 4
+        if batched:
+            nbuf = max(nbuf, 2 * max_in_flight * max(t["views_per_frame"] for t in tuned))
+        sat, ovf_s = saturation(srv, nbuf)
+        lat, tr, kept = latency(srv, max(load * sat, 1.0), nbuf, keep=set(range(0, 400, 37)))
         st = srv.stats()
         srv.close()
-        in_win = [r.id for r in trace if r.arrival >= warm]
-        served = sum(1 for d in done_at.values() if warm <= d < warm + measured) / measured
-        l = np.array([lat.get(i, np.inf) for i in in_win])
-        return {"served_fps": round(served, 1), "completed": len(lat), "requests": len(trace),
-                "unfinished_in_window": int(np.isinf(l).sum()),
-                "p50_ms": round(float(np.percentile(l, 50)) * 1e3, 2),
-                "p99_ms": round(float(np.percentile(l, 99)) * 1e3, 2) if np.isfinite(np.percentile(l, 99)) else None,
-                "mean_gpu_ms": round(float(np.mean(gpu_ms)), 4), "overflow_frames": overflow,
-                "contexts": st.contexts, "context_gb": round(st.bytes / 2**30, 2)}
-
-    out = {"workload": f"4 resident scenes (0.5M/1.5M/3M/5.8M), Poisson {rate:.0f} req/s, 720p/1080p/4K, "
-                       f"{warm:.0f} s warm-up + {measured:.0f} s measured",
-           "mixed": run(max_in_flight), "plain": run(1), "max_in_flight": max_in_flight}
+        # served images against the same requests rendered alone
+        same = 0
+        ctxs = {}
+        for rid, img in kept.items():
+            r = tr[rid]
+            w, h = res[r.cls]
+            if r.cls not in ctxs:
+                ctxs[r.cls] = higs.Context(nmax, w, h, max_pairs=classes[r.cls][2])
+            alone, _ = higs.render(ctxs[r.cls], tens[r.scene], r.camera, with_T=False)
+            same += int(torch.equal(alone, img))
+        for c in ctxs.values():
+            c.close()
+        out[name] = {"saturation_fps": round(sat, 1), "saturation_overflow_frames": ovf_s, "latency": lat,
+                     "frames_launched": int(st.frames), "contexts": int(st.contexts),
+                     "context_gb": round(st.bytes / 2**30, 2), "served_equals_alone": f"{same}/{len(kept)}"}
+        if tuned:
+            out[name]["tuned"] = tuned
+        log(f"serving {name}: {out[name]}")
     return out
 
 

@@ -92,6 +92,7 @@ typedef struct {
   int32_t raster_precision; /* HIGS_RASTER_FP32 (default) or HIGS_RASTER_FP16 */
   int32_t sh_format;  /* HIGS_SH_FLOAT32 (default) or HIGS_SH_PACKED32 */
   int32_t max_views;  /* views one frame of higs_render_views may hold, 1..HIGS_MAX_VIEWS (1) */
+  int32_t use_graphs; /* 1: replay frames from HIP graphs (see below); 0 (default): launch each kernel */
 } higs_params;
 
 #define HIGS_MAX_VIEWS 64
@@ -144,7 +145,7 @@ typedef struct {
                               writes: 8 when key and gaussian id share one
                               64-bit word, 12 when the id travels in an array
                               of its own; 0 in segmented mode */
-  int32_t reserved;
+  int32_t graphs;       /* HIP graphs the context holds (params->use_graphs) */
 } higs_counts;
 
 /* Writes the paper's defaults into *p. */
@@ -225,6 +226,21 @@ typedef struct {
 } higs_view;
 int higs_render_views(higs_ctx* ctx, int32_t n_views, const higs_view* views, void* stream);
 
+/* Graph replay (params->use_graphs = 1): higs_render and higs_render_views
+ * record a frame of each new shape (view count, the frame's largest scene
+ * rounded up to 1,024 gaussians, image size) into a HIP graph on first use and
+ * replay it afterwards, one launch per frame.  The graph's kernels read the
+ * views (scene arrays, camera, image) from a device table that the graph's
+ * first node copies from a pinned host buffer of that graph; before writing
+ * the buffer the call waits for the graph's previous replay to complete, so
+ * frames of one shape on one context do not overlap on the host.  The image
+ * is the one the per-kernel launch gives, bit for bit.  Frames on the legacy
+ * default stream (stream = NULL), with timers (higs_set_timing) or debug
+ * flags, and in the segmented sort mode launch kernel by kernel.  A context
+ * keeps at most 32 graphs (least recently used are destroyed).  Only
+ * higs_render and higs_render_views replay; the staged calls (higs_project
+ * ...) always launch kernel by kernel. */
+
 /* Adjoint of the last frame rendered on ctx (the paper is forward-only; its
  * Forward-only paragraph outlines this backward: the post-blend merge of
  * Eq. 1 becomes a prefix scan of transmittance over the batches, the point
@@ -292,15 +308,19 @@ int higs_render_noalloc(int64_t n, const float* means, const float* scales, cons
 /* ---- Serving ---------------------------------------------------------------
  * A render server keeps several scenes resident on the device and renders a
  * stream of requests (scene, camera, resolution class) with continuous
- * batching: a request is admitted as soon as a frame context of its resolution
- * class is idle, or a new one fits the server's HBM budget (idle contexts of
- * other classes are released to make room, least recently used first; each
- * context's size is higs_ctx_footprint of its class capacities).  Every
- * context renders on a HIP stream of its own, so admitted frames overlap on
- * the device.  The server is driven from one host thread: higs_server_submit
- * queues, higs_server_poll retires finished frames and admits queued ones;
- * neither blocks (releasing a context for the budget synchronises the device).
- * A request's image is the same rendered alone or in the mix.  The paper
+ * batching.  Its frame contexts live in one device arena of hbm_budget bytes,
+ * allocated by higs_server_create: a request is admitted as soon as a context
+ * of its resolution class is idle, or a new one's range fits the arena (idle
+ * contexts of other classes are released to make room, least recently used
+ * first); no device memory is allocated or freed while serving.  An admitted
+ * frame also takes the next queued requests of the same class and image size,
+ * up to the class's views per frame, and renders them in one launch per
+ * kernel (higs_render_views).  Every context renders on a HIP stream of its
+ * own, so admitted frames overlap on the device; with use_graphs the frames
+ * are replayed from HIP graphs.  The server is driven from one host thread:
+ * higs_server_submit queues, higs_server_poll retires finished frames and
+ * admits queued ones; neither blocks.  A request's image is the same rendered
+ * alone (higs_render with the class's batch_cap) or in the mix.  The paper
  * renders single frames; this is the serving loop around its frame path. */
 typedef struct higs_server higs_server;
 
@@ -309,42 +329,83 @@ typedef struct {
   int32_t n_classes;                     /* resolution classes, 1..HIGS_MAX_CLASSES */
   int32_t width[HIGS_MAX_CLASSES];       /* largest image of each class */
   int32_t height[HIGS_MAX_CLASSES];
-  int64_t max_pairs[HIGS_MAX_CLASSES];   /* pair capacity of a context of the class */
+  int64_t max_pairs[HIGS_MAX_CLASSES];   /* pair capacity per view of the class */
   int64_t max_gaussians;                 /* the largest scene */
-  int64_t hbm_budget;                    /* bytes of frame contexts the server may hold */
-  int32_t max_in_flight;                 /* frames rendering at once (1: the plain
-                                            one-frame-at-a-time renderer) */
+  int64_t hbm_budget;                    /* bytes of the context arena (allocated at once) */
+  int32_t max_in_flight;                 /* frames rendering at once (1 with one view per
+                                            frame: the plain one-frame-at-a-time renderer) */
+  int32_t views_per_frame[HIGS_MAX_CLASSES]; /* requests one frame may hold (0 or 1: one);
+                                            higs_server_tune or _set_class may change it */
+  int32_t use_graphs;                    /* 1: frames replayed from HIP graphs */
 } higs_server_config;
 
 typedef struct {
   int64_t request_id;
-  float gpu_ms;       /* device time of the frame, events on its stream */
-  uint32_t overflow;  /* HIGS_OVF_* bits of the frame (its image is then NaN) */
+  float gpu_ms;       /* device time of the request's frame, events on its stream */
+  uint32_t overflow;  /* HIGS_OVF_* bits of the frame (its images are then NaN) */
   int32_t cls;
+  int32_t views;      /* requests the frame rendered */
 } higs_completion;
 
 typedef struct {
   int32_t queued, in_flight, contexts;
-  int64_t bytes;      /* device memory held by frame contexts */
+  int64_t bytes;      /* arena bytes held by frame contexts */
   int64_t completed, evictions;
+  int64_t frames;     /* frames launched (each renders 1..views_per_frame requests) */
+  int32_t views_per_frame[HIGS_MAX_CLASSES];
+  int32_t batch_cap[HIGS_MAX_CLASSES];
 } higs_server_stats;
 
-/* params: NULL for the defaults; the scene arrays of higs_server_add_scene are
- * device pointers owned by the caller that must stay valid and unchanged while
- * the server renders them.  image of higs_server_submit: device [H, W, 3] of
- * the camera's size (at most the class size, else HIGS_E_CAPACITY), written
- * when the request completes.  higs_server_poll returns the number of
- * completions written to done (<= max_done), or a negative error. */
+/* params: NULL for the defaults.  HIGS_E_NOMEM if the arena cannot be
+ * allocated.
+ * higs_server_add_scene: the scene arrays are device pointers owned by the
+ * caller that must stay valid and unchanged while the server renders them;
+ * stream: the stream on which the arrays were written (an event recorded on it
+ * now orders every frame of the scene after that work; NULL is the legacy
+ * default stream).
+ * higs_server_submit: image is device [H, W, 3] of the camera's size (at most
+ * the class size, else HIGS_E_CAPACITY), written when the request completes;
+ * stream: the caller's stream whose work so far must precede the frame (an
+ * event is recorded on it now; NULL is the legacy default stream).  The image
+ * is final once higs_server_poll has returned the request.
+ * higs_server_poll returns the number of completions written to done
+ * (<= max_done; completions of a frame that do not fit wait for the next
+ * call), or a negative error; an error met after completions were retired is
+ * returned by the next call that has none to report. */
 int higs_server_create(int device, const higs_params* params, const higs_server_config* cfg,
                        higs_server** out);
 int higs_server_destroy(higs_server* server);
 int higs_server_add_scene(higs_server* server, int32_t scene_id, int64_t n, const float* means,
                           const float* scales, const float* quats, const float* opacities,
-                          const float* sh);
+                          const float* sh, void* stream);
 int higs_server_submit(higs_server* server, int64_t request_id, int32_t scene_id, int32_t cls,
-                       const higs_camera* cam, float* image);
+                       const higs_camera* cam, float* image, void* stream);
 int higs_server_poll(higs_server* server, higs_completion* done, int32_t max_done);
 int higs_server_get_stats(higs_server* server, higs_server_stats* out);
+
+/* Autotuner: for class cls, renders `frames` frames of scene_id at the
+ * cameras given (cycled; each of the class size) for every candidate of
+ * views per frame in {1, 2, 4, 8, 16} (those whose context fits the arena)
+ * and, with allow_batch_cap, B_r in {1024, 512, 256} (other values change the
+ * batch boundaries, so images are then no longer those of B_r = 1024 bit for
+ * bit); each trial keeps max_in_flight frames in flight on as many contexts as
+ * fit.  The fastest (requests per second) becomes the class's setting.  The
+ * server must be idle (HIGS_E_STATE otherwise); its idle contexts are
+ * released.  Synchronises the device. */
+#define HIGS_TUNE_MAX_TRIALS 16
+typedef struct {
+  int32_t views_per_frame, batch_cap;   /* chosen */
+  int32_t n_trials;
+  int32_t trial_views[HIGS_TUNE_MAX_TRIALS];
+  int32_t trial_batch_cap[HIGS_TUNE_MAX_TRIALS];
+  float trial_fps[HIGS_TUNE_MAX_TRIALS];   /* requests per second */
+} higs_tune_report;
+int higs_server_tune(higs_server* server, int32_t cls, int32_t scene_id, int32_t n_cams,
+                     const higs_camera* cams, int32_t frames, int32_t allow_batch_cap,
+                     higs_tune_report* out);
+/* Sets a class's views per frame and B_r for contexts created from now on. */
+int higs_server_set_class(higs_server* server, int32_t cls, int32_t views_per_frame,
+                          int32_t batch_cap);
 
 /* Synchronises the stream of the last call and reports the frame's sizes. */
 int higs_get_counts(higs_ctx* ctx, higs_counts* out);

@@ -29,11 +29,17 @@ __global__ void clear_kernel(DeviceCounters* dc, uint32_t* hist, int n_hist, uin
                              int n_seg) {
   uint32_t* w = reinterpret_cast<uint32_t*>(dc);
   const int nw = (int)(sizeof(DeviceCounters) / 4);
-  for (int k = threadIdx.x; k < nw; k += blockDim.x) w[k] = 0;
+  const int keep = (int)(offsetof(DeviceCounters, epoch) / 4);
+  for (int k = threadIdx.x; k < nw; k += blockDim.x)
+    if (k != keep) w[k] = 0;
   for (int k = threadIdx.x; k < n_hist; k += blockDim.x) hist[k] = 0;
   for (int k = threadIdx.x; k < n_seg; k += blockDim.x) seg_count[k] = 0;
   __syncthreads();
-  if (threadIdx.x == 0) dc->key_min = 0xffffffffu;
+  if (threadIdx.x == 0) {
+    dc->key_min = 0xffffffffu;
+    // this frame's sort passes publish under epochs epoch .. epoch + kMaxPasses - 1
+    dc->epoch += (uint32_t)kMaxPasses;
+  }
 }
 
 hipError_t launch_clear(DeviceCounters* dc, uint32_t* hist, int n_hist, uint32_t* seg_count,

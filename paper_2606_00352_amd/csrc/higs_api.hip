@@ -18,6 +18,7 @@
 using namespace higs;
 
 constexpr int kViewRing = 4;
+constexpr size_t kMaxGraphs = 32;  // graphs a context keeps (least recently used go)
 
 struct higs_ctx {
   int device = 0;
@@ -71,7 +72,22 @@ struct higs_ctx {
   ViewArgs* view_stage = nullptr;  // [kViewRing][max_views] pinned host slots
   hipEvent_t view_ev[kViewRing] = {};
   int view_slot = 0;
-  uint32_t epoch = 1;  // sort look-back epochs
+  uint64_t epoch_frames = 0;  // frames since the look-back words were last untagged
+  // frames replayed from graphs (params.use_graphs): one graph per frame shape
+  struct Graph {
+    int32_t n_views = 0, width = 0, height = 0;
+    int64_t n_pad = 0;
+    hipGraphExec_t exec = nullptr;
+    ViewArgs* stage = nullptr;  // pinned slice [n_views] of graph_stage: each replay copies
+                                //   it to view_table
+    hipEvent_t done = nullptr;  // after the last replay: the stage may be rewritten
+    bool launched = false;
+    uint64_t last_used = 0;
+  };
+  std::vector<Graph> graphs;
+  uint64_t graph_tick = 0;
+  ViewArgs* graph_stage = nullptr;  // pinned [kMaxGraphs][max_views]: the graphs' stages
+  bool external = false;  // buffers carved from a caller's arena (not freed here)
   hipStream_t last_stream = nullptr;
   int debug_flags = 0;
   // timing: events of the last `ring` frames, frame f in slot f % ring
@@ -91,6 +107,15 @@ namespace {
 __global__ void zero_words_kernel(uint64_t* __restrict__ p, size_t n) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0ull;
+}
+
+__global__ void epoch_reset_kernel(DeviceCounters* __restrict__ dc) { dc->epoch = 0; }
+
+void destroy_graph(higs_ctx::Graph& g) {
+  if (g.launched && g.done) (void)hipEventSynchronize(g.done);
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.done) (void)hipEventDestroy(g.done);
+  g = higs_ctx::Graph();
 }
 
 hipError_t launch_zero_words(uint64_t* p, size_t n, hipStream_t s) {
@@ -136,15 +161,23 @@ void free_events(higs_ctx* c) {
 }
 
 void free_all(higs_ctx* c) {
-  void* bufs[] = {c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau, c->f_key, c->f_cnt, c->f_span,
-                  c->rec, c->block_sums, c->keys[0], c->keys[1], c->vals[0], c->vals[1],
-                  c->dbg_keys, c->dbg_vals, c->hist, c->plan, c->status, c->mt_off,
-                  c->batch_first, c->batch_tab, c->active, c->partials, c->dc,
-                  c->bwd_state, c->dgeo, c->seg_count, c->seg_cursor, c->seg_chunk_off,
-                  c->seg_blk_off, c->view_table};
-  for (void* b : bufs)
+  // buffers allocated on demand (debug read-back, the adjoint's state)
+  void* extra[] = {c->dbg_keys, c->dbg_vals, c->bwd_state, c->dgeo};
+  for (void* b : extra)
     if (b) (void)hipFree(b);
+  if (!c->external) {
+    void* bufs[] = {c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau, c->f_key, c->f_cnt,
+                    c->f_span, c->rec, c->block_sums, c->keys[0], c->keys[1], c->vals[0],
+                    c->vals[1], c->hist, c->plan, c->status, c->mt_off, c->batch_first,
+                    c->batch_tab, c->active, c->partials, c->dc, c->seg_count, c->seg_cursor,
+                    c->seg_chunk_off, c->seg_blk_off, c->view_table};
+    for (void* b : bufs)
+      if (b) (void)hipFree(b);
+  }
+  for (higs_ctx::Graph& g : c->graphs) destroy_graph(g);
+  c->graphs.clear();
   if (c->view_stage) (void)hipHostFree(c->view_stage);
+  if (c->graph_stage) (void)hipHostFree(c->graph_stage);
   for (hipEvent_t& e : c->view_ev)
     if (e) (void)hipEventDestroy(e);
   free_events(c);
@@ -197,6 +230,24 @@ void for_each_buffer(higs_ctx* c, F&& f) {
   f(&c->seg_chunk_off, mt + 1);
   f(&c->seg_blk_off, mt + 1);
   f(&c->view_table, (size_t)c->params.max_views);
+}
+
+// Lays the context's buffers out in [base, base + cap), 256-byte aligned.
+bool carve(higs_ctx* c, unsigned char* base, size_t cap) {
+  size_t off = 0;
+  bool fits = true;
+  for_each_buffer(c, [&](auto** ptr, size_t count) {
+    using T = typename std::remove_reference<decltype(**ptr)>::type;
+    const size_t bytes = ((count ? count : 1) * sizeof(T) + 255) & ~(size_t)255;
+    if (off + bytes > cap) {
+      fits = false;
+      *ptr = nullptr;
+      return;
+    }
+    *ptr = reinterpret_cast<T*>(base + off);
+    off += bytes;
+  });
+  return fits;
 }
 
 void set_capacities(higs_ctx* c, int64_t max_gaussians, int64_t max_pairs, int64_t max_batches,
@@ -259,6 +310,7 @@ void higs_default_params(higs_params* p) {
   p->raster_precision = HIGS_RASTER_FP32;
   p->sh_format = HIGS_SH_FLOAT32;
   p->max_views = 1;
+  p->use_graphs = 0;
 }
 
 const char* higs_error_string(int code) {
@@ -274,14 +326,11 @@ const char* higs_error_string(int code) {
   }
 }
 
-int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians,
-                    int64_t max_pairs, int64_t max_batches, int32_t max_width,
-                    int32_t max_height, higs_ctx** out) {
-  if (!out) return HIGS_E_INVALID;
-  *out = nullptr;
-  higs_params p;
-  if (params) p = *params;
-  else higs_default_params(&p);
+}  // extern "C"
+
+namespace {
+int check_params(const higs_params& p, int64_t max_gaussians, int64_t max_pairs,
+                 int64_t max_batches, int32_t max_width, int32_t max_height) {
   if (p.tile_px != kTile || p.mt_tiles_x != kMtTilesX || p.mt_tiles_y != kMtTilesY)
     return HIGS_E_UNSUPPORTED;
   if (p.sh_degree < 0 || p.sh_degree > 3) return HIGS_E_UNSUPPORTED;
@@ -304,9 +353,59 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
   if (max_gaussians > (int64_t)0x7fffffff || max_pairs > (int64_t)0xfffff000 ||
       max_batches > (int64_t)0x7fffffff)
     return HIGS_E_INVALID;
+  // virtual gaussian ids (the view's range, then the gaussian) are 32-bit
+  if ((int64_t)p.max_views * pad_blocks(max_gaussians) > (int64_t)0xffffffff) return HIGS_E_INVALID;
+  if (p.use_graphs != 0 && p.use_graphs != 1) return HIGS_E_INVALID;
+  return HIGS_OK;
+}
+
+// Device bytes of a context laid out by carve (every buffer 256-byte aligned).
+int64_t carved_bytes(higs_ctx* c) {
+  int64_t bytes = 0;
+  for_each_buffer(c, [&](auto** ptr, size_t count) {
+    bytes += (int64_t)((((count ? count : 1) * sizeof(**ptr)) + 255) & ~(size_t)255);
+  });
+  return bytes;
+}
+
+// Host-side state of a new context: pinned view-table slots and their events.
+bool init_host_state(higs_ctx* c) {
+  const higs_params& p = c->params;
+  bool ok = true;
+  if (p.max_views > 1) {
+    ok = hipHostMalloc(reinterpret_cast<void**>(&c->view_stage),
+                       sizeof(ViewArgs) * (size_t)p.max_views * kViewRing,
+                       hipHostMallocDefault) == hipSuccess;
+    for (int k = 0; ok && k < kViewRing; ++k)
+      ok = hipEventCreateWithFlags(&c->view_ev[k], hipEventDisableTiming) == hipSuccess;
+  }
+  if (ok && p.use_graphs)
+    ok = hipHostMalloc(reinterpret_cast<void**>(&c->graph_stage),
+                       sizeof(ViewArgs) * (size_t)p.max_views * kMaxGraphs,
+                       hipHostMallocDefault) == hipSuccess;
+  return ok;
+}
+
+// A context with its buffers in [arena, arena + arena_bytes) (null arena:
+// buffers of its own).  An arena context's look-back words and counters are
+// zeroed by kernels on stream s, with no host synchronisation.
+int create_ctx(int device, const higs_params* params, int64_t max_gaussians, int64_t max_pairs,
+               int64_t max_batches, int32_t max_width, int32_t max_height, unsigned char* arena,
+               size_t arena_bytes, hipStream_t s, higs_ctx** out) {
+  if (!out) return HIGS_E_INVALID;
+  *out = nullptr;
+  higs_params p;
+  if (params) p = *params;
+  else higs_default_params(&p);
+  int rc = check_params(p, max_gaussians, max_pairs, max_batches, max_width, max_height);
+  if (rc) return rc;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HIGS_E_INVALID;
   DeviceGuard g(device);
+  // launch shapes of the persistent kernels, before any capture reads them
+  (void)raster_per_cu_config();
+  (void)raster16_per_cu_config();
+  (void)onesweep_per_cu_config();
   higs_ctx* c = new (std::nothrow) higs_ctx();
   if (!c) return HIGS_E_NOMEM;
   c->device = device;
@@ -318,31 +417,39 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
     return HIGS_E_HIP;
   }
   c->n_cus = prop.multiProcessorCount;
-  int rc = HIGS_OK;
-  for_each_buffer(c, [&](auto** ptr, size_t count) { rc |= dalloc(ptr, count); });
-  if (rc != HIGS_OK) {
-    free_all(c);
-    delete c;
-    return HIGS_E_NOMEM;
+  bool ok;
+  if (arena) {
+    c->external = true;
+    ok = carve(c, arena, arena_bytes);
+    if (!ok) {
+      free_all(c);
+      delete c;
+      return HIGS_E_CAPACITY;
+    }
+    // look-back words start untagged (epoch 0 never matches a pass)
+    ok = launch_zero_words(c->status, (size_t)c->max_tiles * kRadix, s) == hipSuccess &&
+         launch_zero_words(reinterpret_cast<uint64_t*>(c->dc), sizeof(DeviceCounters) / 8, s) ==
+             hipSuccess;
+  } else {
+    rc = HIGS_OK;
+    for_each_buffer(c, [&](auto** ptr, size_t count) { rc |= dalloc(ptr, count); });
+    if (rc != HIGS_OK) {
+      free_all(c);
+      delete c;
+      return HIGS_E_NOMEM;
+    }
+    // look-back words start untagged (epoch 0 never matches a pass); cleared on
+    // a stream of the context's own, so that creating a context does not wait for
+    // work in flight on other streams
+    hipStream_t init = nullptr;
+    ok = hipStreamCreateWithFlags(&init, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipMemsetAsync(c->status, 0, (size_t)c->max_tiles * kRadix * sizeof(uint64_t),
+                              init) == hipSuccess;
+    ok = ok && hipMemsetAsync(c->dc, 0, sizeof(DeviceCounters), init) == hipSuccess;
+    ok = ok && hipStreamSynchronize(init) == hipSuccess;
+    if (init) (void)hipStreamDestroy(init);
   }
-  // look-back words start untagged (epoch 0 never matches a pass); cleared on
-  // a stream of the context's own, so that creating a context does not wait for
-  // work in flight on other streams
-  hipStream_t init = nullptr;
-  bool ok = hipStreamCreateWithFlags(&init, hipStreamNonBlocking) == hipSuccess;
-  ok = ok && hipMemsetAsync(c->status, 0, (size_t)c->max_tiles * kRadix * sizeof(uint64_t),
-                            init) == hipSuccess;
-  ok = ok && hipMemsetAsync(c->dc, 0, sizeof(DeviceCounters), init) == hipSuccess;
-  ok = ok && hipStreamSynchronize(init) == hipSuccess;
-  if (init) (void)hipStreamDestroy(init);
-  // several views: pinned slots from which each frame's view table is copied
-  if (ok && p.max_views > 1) {
-    ok = hipHostMalloc(reinterpret_cast<void**>(&c->view_stage),
-                       sizeof(ViewArgs) * (size_t)p.max_views * kViewRing,
-                       hipHostMallocDefault) == hipSuccess;
-    for (int k = 0; ok && k < kViewRing; ++k)
-      ok = hipEventCreateWithFlags(&c->view_ev[k], hipEventDisableTiming) == hipSuccess;
-  }
+  ok = ok && init_host_state(c);
   if (!ok) {
     free_all(c);
     delete c;
@@ -350,6 +457,45 @@ int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians
   }
   *out = c;
   return HIGS_OK;
+}
+}  // namespace
+
+namespace higs {
+int64_t ctx_arena_bytes(const higs_params* params, int64_t max_gaussians, int64_t max_pairs,
+                        int64_t max_batches, int32_t max_width, int32_t max_height) {
+  higs_ctx c;
+  if (params) c.params = *params;
+  else higs_default_params(&c.params);
+  const int rc = check_params(c.params, max_gaussians, max_pairs, max_batches, max_width, max_height);
+  if (rc) return rc;
+  set_capacities(&c, max_gaussians, max_pairs, max_batches, max_width, max_height);
+  return carved_bytes(&c);
+}
+
+int ctx_create_in(int device, const higs_params* params, int64_t max_gaussians,
+                  int64_t max_pairs, int64_t max_batches, int32_t max_width, int32_t max_height,
+                  void* arena, size_t arena_bytes, hipStream_t s, higs_ctx** out) {
+  if (!arena) return HIGS_E_INVALID;
+  return create_ctx(device, params, max_gaussians, max_pairs, max_batches, max_width, max_height,
+                    static_cast<unsigned char*>(arena), arena_bytes, s, out);
+}
+
+int ctx_release(higs_ctx* c) {
+  if (!c) return HIGS_E_INVALID;
+  DeviceGuard g(c->device);
+  free_all(c);
+  delete c;
+  return HIGS_OK;
+}
+}  // namespace higs
+
+extern "C" {
+
+int higs_ctx_create(int device, const higs_params* params, int64_t max_gaussians,
+                    int64_t max_pairs, int64_t max_batches, int32_t max_width,
+                    int32_t max_height, higs_ctx** out) {
+  return create_ctx(device, params, max_gaussians, max_pairs, max_batches, max_width, max_height,
+                    nullptr, 0, nullptr, out);
 }
 
 int64_t higs_ctx_footprint(const higs_params* params, int64_t max_gaussians, int64_t max_pairs,
@@ -428,6 +574,20 @@ void fill_view(ViewArgs& w, const higs_camera* cam) {
   }
 }
 
+ViewArgs view_args(const higs_view& w) {
+  ViewArgs a{};
+  a.means = w.means;
+  a.scales = w.scales;
+  a.quats = w.quats;
+  a.opac = w.opacities;
+  a.sh = w.sh;
+  a.n = w.n;
+  a.image = w.image;
+  a.T = w.T_out;
+  fill_view(a, &w.camera);
+  return a;
+}
+
 int check_camera(const higs_ctx* c, const higs_camera* cam) {
   if (!cam || cam->width < 1 || cam->height < 1) return HIGS_E_INVALID;
   if (!(cam->fx > 0.0f) || !(cam->fy > 0.0f)) return HIGS_E_INVALID;
@@ -435,10 +595,29 @@ int check_camera(const higs_ctx* c, const higs_camera* cam) {
   return HIGS_OK;
 }
 
+// The look-back status words carry 30 epoch bits and every frame advances the
+// epoch by kMaxPasses (its clear kernel does): before the epoch could wrap,
+// the words go back to untagged and the epoch to zero, by kernels on the
+// frame's stream ahead of the frame.
+int epoch_guard(higs_ctx* c, hipStream_t s) {
+  constexpr uint64_t kFramesPerCycle = ((1u << 30) - 2u * kMaxPasses) / kMaxPasses;
+  if (++c->epoch_frames < kFramesPerCycle) return HIGS_OK;
+  c->epoch_frames = 1;
+  int rc = hip_err(launch_zero_words(c->status, (size_t)c->max_tiles * kRadix, s));
+  if (rc) return rc;
+  hipLaunchKernelGGL(epoch_reset_kernel, dim3(1), dim3(1), 0, s, c->dc);
+  return hip_err(hipGetLastError());
+}
+
 // Stage 1 for the frame's views (set in c->views): shared geometry, counters,
-// the projection of every view in one launch.
-int project_frame(higs_ctx* c, const higs_camera* cam0, hipStream_t s) {
+// the projection of every view in one launch.  capturing: the frame is being
+// recorded into a graph (its replays run the epoch guard themselves).
+int project_frame(higs_ctx* c, const higs_camera* cam0, hipStream_t s, bool capturing = false) {
   c->last_stream = s;
+  if (!capturing) {
+    const int rc = epoch_guard(c, s);
+    if (rc) return rc;
+  }
   c->stage = 0;
   if (c->timing()) c->frames += 1;
   c->cam = *cam0;
@@ -610,19 +789,10 @@ int higs_bin_sort(higs_ctx* c, void* stream) {
   sb.max_tiles = c->max_tiles;
   {
     TimerScope ts(c, HIGS_TIMER_SORT, s);
-    rc = hip_err(launch_sort(c->n_passes, n_bits((uint32_t)(c->n_mt_all - 1)), c->epoch, sb, c->dc,
+    rc = hip_err(launch_sort(c->n_passes, n_bits((uint32_t)(c->n_mt_all - 1)), sb, c->dc,
                              c->n_cus, s));
   }
-  c->epoch += (uint32_t)c->n_passes;
   if (rc) return rc;
-  if (c->epoch >= (1u << 30) - 64) {
-    // status words hold 30 epoch bits: before the epochs start again at 1,
-    // every word goes back to untagged, so that no word of an early frame
-    // can pass for one published by a later pass with the same epoch
-    c->epoch = 1;
-    rc = hip_err(launch_zero_words(c->status, (size_t)c->max_tiles * kRadix, s));
-    if (rc) return rc;
-  }
   c->stage = 2;
   return HIGS_OK;
 }
@@ -683,6 +853,95 @@ int raster_frame(higs_ctx* c, hipStream_t s) {
   c->stage = 4;
   return HIGS_OK;
 }
+
+// A frame is replayed from a graph when the context asks for it, the stream
+// can be captured (not the legacy default stream) and no timers or debug
+// outputs are on (their events and copies vary from frame to frame).
+bool graph_frame(const higs_ctx* c, hipStream_t s) {
+  return c->params.use_graphs && s != nullptr && !c->timing() && c->debug_flags == 0 &&
+         !c->segmented();
+}
+
+// The frame of views va[0 .. n_views) from the graph of its shape (views,
+// virtual range, image size), recorded on first use: every argument of its
+// kernels is fixed, and what varies per frame (scene arrays, cameras, images)
+// reaches them through the view table, which the graph's first node copies
+// from the graph's pinned stage.
+int render_graph(higs_ctx* c, int n_views, const ViewArgs* va, const higs_camera* cam0,
+                 hipStream_t s) {
+  const size_t bytes = sizeof(ViewArgs) * (size_t)n_views;
+  int gi = -1;
+  for (size_t k = 0; k < c->graphs.size(); ++k) {
+    const higs_ctx::Graph& g = c->graphs[k];
+    if (g.n_views == n_views && g.n_pad == c->n_pad && g.width == cam0->width &&
+        g.height == cam0->height) {
+      gi = (int)k;
+      break;
+    }
+  }
+  if (gi < 0) {
+    if (c->graphs.size() >= kMaxGraphs) {
+      size_t lru = 0;
+      for (size_t k = 1; k < c->graphs.size(); ++k)
+        if (c->graphs[k].last_used < c->graphs[lru].last_used) lru = k;
+      destroy_graph(c->graphs[lru]);
+      c->graphs.erase(c->graphs.begin() + (long)lru);
+    }
+    higs_ctx::Graph g;
+    g.n_views = n_views;
+    g.n_pad = c->n_pad;
+    g.width = cam0->width;
+    g.height = cam0->height;
+    // the first stage slice no held graph uses
+    for (size_t k = 0; k < kMaxGraphs && !g.stage; ++k) {
+      ViewArgs* cand = c->graph_stage + k * (size_t)c->params.max_views;
+      bool used = false;
+      for (const higs_ctx::Graph& h : c->graphs) used = used || h.stage == cand;
+      if (!used) g.stage = cand;
+    }
+    if (!g.stage || hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess) {
+      destroy_graph(g);
+      return HIGS_E_NOMEM;
+    }
+    c->views.count = n_views;
+    c->views.table = c->view_table;
+    c->views.v0 = va[0];
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      destroy_graph(g);
+      return HIGS_E_HIP;
+    }
+    int rc = hip_err(hipMemcpyAsync(c->view_table, g.stage, bytes, hipMemcpyHostToDevice, s));
+    if (!rc) rc = project_frame(c, cam0, s, true);
+    if (!rc) rc = higs_bin_sort(c, s);
+    if (!rc) rc = higs_batch(c, s);
+    if (!rc) rc = raster_frame(c, s);
+    hipGraph_t graph = nullptr;
+    if (hipStreamEndCapture(s, &graph) != hipSuccess && !rc) rc = HIGS_E_HIP;
+    if (!rc && hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) != hipSuccess)
+      rc = HIGS_E_HIP;
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc) {
+      destroy_graph(g);
+      c->stage = 0;
+      return rc;
+    }
+    c->graphs.push_back(g);
+    gi = (int)c->graphs.size() - 1;
+  }
+  higs_ctx::Graph& g = c->graphs[(size_t)gi];
+  // the last replay's copy has read the stage once its event completed
+  if (g.launched && hipEventSynchronize(g.done) != hipSuccess) return HIGS_E_HIP;
+  memcpy(g.stage, va, bytes);
+  int rc = epoch_guard(c, s);
+  if (rc) return rc;
+  if (hipGraphLaunch(g.exec, s) != hipSuccess) return HIGS_E_HIP;
+  if (hipEventRecord(g.done, s) != hipSuccess) return HIGS_E_HIP;
+  g.launched = true;
+  g.last_used = ++c->graph_tick;
+  c->last_stream = s;
+  c->stage = 4;
+  return HIGS_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -700,6 +959,19 @@ int higs_render(higs_ctx* c, int64_t n, const float* means, const float* scales,
                 const float* quats, const float* opacities, const float* sh,
                 const higs_camera* cam, float* image, float* T_out, void* stream) {
   if (!image) return HIGS_E_INVALID;
+  if (c && cam && graph_frame(c, (hipStream_t)stream)) {
+    higs_view v{};
+    v.n = n;
+    v.means = means;
+    v.scales = scales;
+    v.quats = quats;
+    v.opacities = opacities;
+    v.sh = sh;
+    v.camera = *cam;
+    v.image = image;
+    v.T_out = T_out;
+    return higs_render_views(c, 1, &v, stream);
+  }
   int rc = higs_project(c, n, means, scales, quats, opacities, sh, cam, stream);
   if (rc) return rc;
   rc = higs_bin_sort(c, stream);
@@ -735,6 +1007,11 @@ int higs_render_views(higs_ctx* c, int32_t n_views, const higs_view* views, void
   c->in_sh = views[0].sh;
   c->n_views = n_views;
   c->n_pad = pad_blocks(n_max);
+  if (graph_frame(c, s)) {
+    ViewArgs va[HIGS_MAX_VIEWS];
+    for (int v = 0; v < n_views; ++v) va[v] = view_args(views[v]);
+    return render_graph(c, n_views, va, cam0, s);
+  }
   ViewArgs* slot = nullptr;
   if (n_views > 1) {
     // the view table goes to the device from a pinned slot that no earlier
@@ -745,17 +1022,7 @@ int higs_render_views(higs_ctx* c, int32_t n_views, const higs_view* views, void
     slot = c->view_stage + (size_t)k * c->params.max_views;
   }
   for (int v = 0; v < n_views; ++v) {
-    const higs_view& w = views[v];
-    ViewArgs a{};
-    a.means = w.means;
-    a.scales = w.scales;
-    a.quats = w.quats;
-    a.opac = w.opacities;
-    a.sh = w.sh;
-    a.n = w.n;
-    a.image = w.image;
-    a.T = w.T_out;
-    fill_view(a, &w.camera);
+    const ViewArgs a = view_args(views[v]);
     if (v == 0) c->views.v0 = a;
     if (slot) slot[v] = a;
   }
@@ -820,7 +1087,7 @@ int higs_get_counts(higs_ctx* c, higs_counts* out) {
                            ? (int64_t)h.n_evals * 64
                            : -1;
   out->sort_pair_bytes = (c->stage < 2 || c->segmented()) ? 0 : (h.id_shift ? 8 : 12);
-  out->reserved = 0;
+  out->graphs = (int32_t)c->graphs.size();
   return HIGS_OK;
 }
 
@@ -1019,23 +1286,6 @@ struct NoAllocState {
 NoAllocState g_noalloc[kNaMaxDevices];
 std::mutex g_noalloc_mu;
 
-// Lays the context's buffers out in [base, base + cap), 256-byte aligned.
-bool carve(higs_ctx* c, unsigned char* base, size_t cap) {
-  size_t off = 0;
-  bool fits = true;
-  for_each_buffer(c, [&](auto** ptr, size_t count) {
-    using T = typename std::remove_reference<decltype(**ptr)>::type;
-    const size_t bytes = ((count ? count : 1) * sizeof(T) + 255) & ~(size_t)255;
-    if (off + bytes > cap) {
-      fits = false;
-      *ptr = nullptr;
-      return;
-    }
-    *ptr = reinterpret_cast<T*>(base + off);
-    off += bytes;
-  });
-  return fits;
-}
 }  // namespace
 
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "../../include/higs.h"
@@ -68,7 +69,8 @@ struct DeviceCounters {
   uint32_t raster_next;     // work counter of the persistent rasteriser
   uint32_t tile_next[kMaxPasses];  // work counters of the sort passes
   uint32_t sort_passes;     // radix passes that moved data (others skipped)
-  uint32_t reserved0;
+  uint32_t epoch;           // look-back epoch base: each frame's clear advances it by
+                            //   kMaxPasses and leaves it otherwise untouched
   unsigned long long n_evals;  // gaussian-tile evaluations (when counted)
   uint32_t key_min;         // smallest / largest float32 depth bits of the
   uint32_t key_max;         //   frame's visible gaussians (key compression)
@@ -131,8 +133,9 @@ struct ViewArgs {
   float* T;
 };
 
-// The views of a frame: the first by value (every single-view frame), the
-// others from a device table (table[v] for v >= 1; null when V = 1).
+// The views of a frame: from a device table when there is one (several views,
+// or a frame replayed from a graph, whose arguments are fixed), else the one
+// view by value.
 struct Views {
   int32_t count;
   int64_t n_pad;  // virtual gaussians per view: a multiple of kProjBlock * kFillGroup
@@ -140,7 +143,7 @@ struct Views {
   ViewArgs v0;
   const ViewArgs* table;
   __host__ __device__ __forceinline__ const ViewArgs& get(int v) const {
-    return v == 0 ? v0 : table[v];
+    return table ? table[v] : v0;
   }
 };
 
@@ -173,7 +176,7 @@ struct SortBuffers {
   uint64_t* status;      // [max_tiles][kRadix] look-back words
   uint32_t max_tiles;
 };
-hipError_t launch_sort(int n_passes, int mt_bits, uint32_t epoch_base, SortBuffers sb,
+hipError_t launch_sort(int n_passes, int mt_bits, SortBuffers sb,
                        DeviceCounters* dc, int n_cus, hipStream_t s);
 
 hipError_t launch_batch(int n_mt, uint32_t batch_cap, uint32_t max_batches, const uint64_t* const* keys2,
@@ -240,9 +243,26 @@ hipError_t launch_batch_from_offsets(int n_mt, uint32_t batch_cap, uint32_t max_
                                      uint32_t* batch_first, uint32_t* batch_tab, hipStream_t s);
 
 int raster_workers_per_cu();
+// Resident workgroups per CU of the persistent kernels, queried once per
+// process (before any graph capture reads them).
+int raster_per_cu_config();
+int raster16_per_cu_config();
+int onesweep_per_cu_config();
 
 // Enqueues a copy of the context's frame counters into pinned host memory
 // (sizeof(DeviceCounters) bytes) on stream s.
 int ctx_enqueue_counters(higs_ctx* c, void* pinned_dst, hipStream_t s);
+// Contexts in caller-provided device memory (the render server's arena):
+// ctx_arena_bytes is the size ctx_create_in lays the buffers out in (or a
+// negative error for invalid capacities); ctx_create_in zeroes what must start
+// at zero with kernels on stream s; ctx_release frees the host-side state only
+// (no device memory, no device synchronisation: the caller has waited for the
+// context's last frame).
+int64_t ctx_arena_bytes(const higs_params* params, int64_t max_gaussians, int64_t max_pairs,
+                        int64_t max_batches, int32_t max_width, int32_t max_height);
+int ctx_create_in(int device, const higs_params* params, int64_t max_gaussians,
+                  int64_t max_pairs, int64_t max_batches, int32_t max_width, int32_t max_height,
+                  void* arena, size_t arena_bytes, hipStream_t s, higs_ctx** out);
+int ctx_release(higs_ctx* c);
 
 }  // namespace higs

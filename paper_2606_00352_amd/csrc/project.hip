@@ -188,7 +188,7 @@ project_kernel(Views views, CamArgs shape, ParamArgs prm, float* __restrict__ f_
   __shared__ float sh_scale[kShComps];
   const int view = (int)(blockIdx.x % (uint32_t)views.count);
   const int64_t blk = (int64_t)(blockIdx.x / (uint32_t)views.count);
-  const ViewArgs w = view == 0 ? views.v0 : views.table[view];
+  const ViewArgs w = views.get(view);
   const float* __restrict__ means = w.means;
   const float* __restrict__ scales = w.scales;
   const float* __restrict__ quats = w.quats;

@@ -154,7 +154,7 @@ merge_kernel(CamArgs cam, ParamArgs prm, Views views, const uint32_t* __restrict
     cr = cg = cb = T = __builtin_nanf("");
   }
   if (x < cam.width && y < cam.height) {
-    const ViewArgs& w = view == 0 ? views.v0 : views.table[view];
+    const ViewArgs& w = views.get(view);
     float* __restrict__ image = w.image;
     float* __restrict__ T_out = w.T;
     const size_t pix = (size_t)y * cam.width + x;
@@ -167,10 +167,9 @@ merge_kernel(CamArgs cam, ParamArgs prm, Views views, const uint32_t* __restrict
 
 static int g_raster_per_cu = 0;
 
-hipError_t launch_raster(CamArgs cam, ParamArgs prm, const uint32_t* const* vals2,
-                         const RasterRecord* rec, const uint32_t* batch_tab,
-                         DeviceCounters* dc, float4* partials, uint32_t* active, int n_cus,
-                         bool count_evals, hipStream_t s) {
+// Resident raster workgroups per CU (queried once; the launchers read it, also
+// while a stream is being captured into a graph).
+int raster_per_cu_config() {
   if (g_raster_per_cu == 0) {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, raster_kernel<false>, kRasterThreads, 0) !=
@@ -179,6 +178,14 @@ hipError_t launch_raster(CamArgs cam, ParamArgs prm, const uint32_t* const* vals
       nb = 1;
     g_raster_per_cu = nb;
   }
+  return g_raster_per_cu;
+}
+
+hipError_t launch_raster(CamArgs cam, ParamArgs prm, const uint32_t* const* vals2,
+                         const RasterRecord* rec, const uint32_t* batch_tab,
+                         DeviceCounters* dc, float4* partials, uint32_t* active, int n_cus,
+                         bool count_evals, hipStream_t s) {
+  raster_per_cu_config();
   if (count_evals)
     hipLaunchKernelGGL(raster_kernel<true>, dim3(n_cus * g_raster_per_cu), dim3(kRasterThreads), 0, s,
                        cam, prm, vals2[0], vals2[1], rec, batch_tab, dc, partials, active);

@@ -210,7 +210,7 @@ merge16_kernel(CamArgs cam, ParamArgs prm, Views views, const uint32_t* __restri
   const int x = tx * kTile + (lane & 7), y = ty * kTile + (lane >> 3);
   if (dc->overflow) cr = cg = cb = T = __builtin_nanf("");
   if (x < cam.width && y < cam.height) {
-    const ViewArgs& w = view == 0 ? views.v0 : views.table[view];
+    const ViewArgs& w = views.get(view);
     float* __restrict__ image = w.image;
     float* __restrict__ T_out = w.T;
     const size_t pix = (size_t)y * cam.width + x;
@@ -223,10 +223,7 @@ merge16_kernel(CamArgs cam, ParamArgs prm, Views views, const uint32_t* __restri
 
 static int g_r16_per_cu = 0;
 
-hipError_t launch_raster16(CamArgs cam, ParamArgs prm, const uint32_t* const* vals2,
-                           const RasterRecord* rec, const uint32_t* batch_tab, DeviceCounters* dc,
-                           void* partials, uint32_t* active, int n_cus, bool count_evals,
-                           hipStream_t s) {
+int raster16_per_cu_config() {
   if (g_r16_per_cu == 0) {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, raster16_kernel<false>, kR16Threads, 0) !=
@@ -235,6 +232,14 @@ hipError_t launch_raster16(CamArgs cam, ParamArgs prm, const uint32_t* const* va
       nb = 1;
     g_r16_per_cu = nb;
   }
+  return g_r16_per_cu;
+}
+
+hipError_t launch_raster16(CamArgs cam, ParamArgs prm, const uint32_t* const* vals2,
+                           const RasterRecord* rec, const uint32_t* batch_tab, DeviceCounters* dc,
+                           void* partials, uint32_t* active, int n_cus, bool count_evals,
+                           hipStream_t s) {
+  raster16_per_cu_config();
   h4* p = static_cast<h4*>(partials);
   if (count_evals)
     hipLaunchKernelGGL(raster16_kernel<true>, dim3(n_cus * g_r16_per_cu), dim3(kR16Threads), 0, s,

@@ -150,7 +150,7 @@ struct SortLds {
 // four waves per SIMD (two workgroups per CU): the register budget is held to
 // 128, which measured faster than more keys per thread at lower occupancy
 __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)))
-onesweep_kernel(int pass, uint32_t epoch, uint64_t* __restrict__ k0, uint32_t* __restrict__ v0,
+onesweep_kernel(int pass, uint64_t* __restrict__ k0, uint32_t* __restrict__ v0,
                 uint64_t* __restrict__ k1, uint32_t* __restrict__ v1,
                 const uint32_t* __restrict__ plan, const uint32_t* __restrict__ base,
                 uint64_t* __restrict__ status, DeviceCounters* __restrict__ dc) {
@@ -158,6 +158,8 @@ onesweep_kernel(int pass, uint32_t epoch, uint64_t* __restrict__ k0, uint32_t* _
   if (dc->overflow) return;  // (the plan was not written either)
   const uint32_t src = plan[pass];
   if (src == 0xffffffffu) return;  // every key has the same digit: identity pass
+  // the epoch this pass publishes under (the frame's clear set the base)
+  const uint32_t epoch = dc->epoch + (uint32_t)pass;
   const uint64_t* __restrict__ kin = src ? k1 : k0;
   const uint32_t* __restrict__ vin = src ? v1 : v0;
   uint64_t* __restrict__ kout = src ? k0 : k1;
@@ -326,8 +328,7 @@ onesweep_kernel(int pass, uint32_t epoch, uint64_t* __restrict__ k0, uint32_t* _
 
 static int g_onesweep_per_cu = 0;
 
-hipError_t launch_sort(int n_passes, int mt_bits, uint32_t epoch_base, SortBuffers sb,
-                       DeviceCounters* dc, int n_cus, hipStream_t s) {
+int onesweep_per_cu_config() {
   if (g_onesweep_per_cu == 0) {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, onesweep_kernel, kSortThreads, 0) !=
@@ -336,6 +337,12 @@ hipError_t launch_sort(int n_passes, int mt_bits, uint32_t epoch_base, SortBuffe
       nb = 1;
     g_onesweep_per_cu = nb;
   }
+  return g_onesweep_per_cu;
+}
+
+hipError_t launch_sort(int n_passes, int mt_bits, SortBuffers sb,
+                       DeviceCounters* dc, int n_cus, hipStream_t s) {
+  onesweep_per_cu_config();
   hipLaunchKernelGGL(sort_hist_kernel, dim3(n_cus * 2), dim3(kHistThreads), 0, s, sb.keys[0], dc,
                      n_passes, mt_bits, sb.hist);
   hipLaunchKernelGGL(sort_plan_kernel, dim3(1), dim3(kRadix), 0, s, sb.hist, dc, n_passes, mt_bits,
@@ -343,7 +350,7 @@ hipError_t launch_sort(int n_passes, int mt_bits, uint32_t epoch_base, SortBuffe
   const int workers = n_cus * g_onesweep_per_cu;
   for (int p = 0; p < n_passes; ++p) {
     hipLaunchKernelGGL(onesweep_kernel, dim3(workers), dim3(kSortThreads), 0, s, p,
-                       epoch_base + (uint32_t)p, sb.keys[0], sb.vals[0], sb.keys[1], sb.vals[1],
+                       sb.keys[0], sb.vals[0], sb.keys[1], sb.vals[1],
                        sb.plan, sb.plan + kMaxPasses, sb.status, dc);
   }
   return hipGetLastError();

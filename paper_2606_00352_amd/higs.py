@@ -31,7 +31,7 @@ EXPORTS = ("higs_default_params", "higs_ctx_create", "higs_ctx_destroy", "higs_p
            "higs_error_string", "higs_raster_backward", "higs_ctx_footprint",
            "higs_server_create", "higs_server_destroy", "higs_server_add_scene", "higs_server_submit",
            "higs_server_poll", "higs_server_get_stats", "higs_render_noalloc", "higs_sh_packed_bytes",
-           "higs_sh_compress", "higs_render_views")
+           "higs_sh_compress", "higs_render_views", "higs_server_tune", "higs_server_set_class")
 
 
 class HigsError(RuntimeError):
@@ -47,7 +47,7 @@ class Params(ctypes.Structure):
                 ("t_eps", ctypes.c_float), ("near_z", ctypes.c_float),
                 ("dilation", ctypes.c_float), ("sort_mode", ctypes.c_int32),
                 ("raster_precision", ctypes.c_int32), ("sh_format", ctypes.c_int32),
-                ("max_views", ctypes.c_int32)]
+                ("max_views", ctypes.c_int32), ("use_graphs", ctypes.c_int32)]
 
 
 class CameraC(ctypes.Structure):
@@ -62,7 +62,7 @@ class Counts(ctypes.Structure):
                 ("n_pairs", ctypes.c_int64), ("n_batches", ctypes.c_int64),
                 ("overflow", ctypes.c_uint32), ("sort_passes", ctypes.c_int32),
                 ("n_evaluations", ctypes.c_int64), ("sort_pair_bytes", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("graphs", ctypes.c_int32)]
 
 
 MAX_CLASSES = 4
@@ -79,17 +79,30 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [("n_classes", ctypes.c_int32), ("width", ctypes.c_int32 * MAX_CLASSES),
                 ("height", ctypes.c_int32 * MAX_CLASSES), ("max_pairs", ctypes.c_int64 * MAX_CLASSES),
                 ("max_gaussians", ctypes.c_int64), ("hbm_budget", ctypes.c_int64),
-                ("max_in_flight", ctypes.c_int32)]
+                ("max_in_flight", ctypes.c_int32), ("views_per_frame", ctypes.c_int32 * MAX_CLASSES),
+                ("use_graphs", ctypes.c_int32)]
 
 
 class Completion(ctypes.Structure):
     _fields_ = [("request_id", ctypes.c_int64), ("gpu_ms", ctypes.c_float),
-                ("overflow", ctypes.c_uint32), ("cls", ctypes.c_int32)]
+                ("overflow", ctypes.c_uint32), ("cls", ctypes.c_int32), ("views", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("queued", ctypes.c_int32), ("in_flight", ctypes.c_int32), ("contexts", ctypes.c_int32),
-                ("bytes", ctypes.c_int64), ("completed", ctypes.c_int64), ("evictions", ctypes.c_int64)]
+                ("bytes", ctypes.c_int64), ("completed", ctypes.c_int64), ("evictions", ctypes.c_int64),
+                ("frames", ctypes.c_int64), ("views_per_frame", ctypes.c_int32 * MAX_CLASSES),
+                ("batch_cap", ctypes.c_int32 * MAX_CLASSES)]
+
+
+TUNE_MAX_TRIALS = 16
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("views_per_frame", ctypes.c_int32), ("batch_cap", ctypes.c_int32),
+                ("n_trials", ctypes.c_int32), ("trial_views", ctypes.c_int32 * TUNE_MAX_TRIALS),
+                ("trial_batch_cap", ctypes.c_int32 * TUNE_MAX_TRIALS),
+                ("trial_fps", ctypes.c_float * TUNE_MAX_TRIALS)]
 
 
 _lib = None
@@ -122,8 +135,10 @@ def lib():
             "higs_ctx_footprint": (i64, [P, i64, i64, i64, i32, i32]),
             "higs_server_create": (ctypes.c_int, [ctypes.c_int, P, P, P]),
             "higs_server_destroy": (ctypes.c_int, [P]),
-            "higs_server_add_scene": (ctypes.c_int, [P, i32, i64, P, P, P, P, P]),
-            "higs_server_submit": (ctypes.c_int, [P, i64, i32, i32, P, P]),
+            "higs_server_add_scene": (ctypes.c_int, [P, i32, i64, P, P, P, P, P, P]),
+            "higs_server_submit": (ctypes.c_int, [P, i64, i32, i32, P, P, P]),
+            "higs_server_tune": (ctypes.c_int, [P, i32, i32, i32, P, i32, i32, P]),
+            "higs_server_set_class": (ctypes.c_int, [P, i32, i32, i32]),
             "higs_server_poll": (ctypes.c_int, [P, P, i32]),
             "higs_server_get_stats": (ctypes.c_int, [P, P]),
             "higs_render_noalloc": (ctypes.c_int, [i64, P, P, P, P, P, P, P, P, P]),
@@ -183,6 +198,9 @@ def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return stream.cuda_stream
+
+
+_dep_stream = _stream
 
 
 class CapacityError(HigsError):
@@ -413,14 +431,16 @@ class Server:
     max_pairs), ...]."""
 
     def __init__(self, classes, max_gaussians: int, hbm_budget: int, max_in_flight: int = 16, device: int = 0,
-                 **params):
+                 views_per_frame=None, use_graphs: bool = False, **params):
         cfg = ServerConfig()
         cfg.n_classes = len(classes)
         for k, (w, h, mp) in enumerate(classes):
             cfg.width[k], cfg.height[k], cfg.max_pairs[k] = int(w), int(h), int(mp)
+            cfg.views_per_frame[k] = int(views_per_frame[k]) if views_per_frame else 1
         cfg.max_gaussians = int(max_gaussians)
         cfg.hbm_budget = int(hbm_budget)
         cfg.max_in_flight = int(max_in_flight)
+        cfg.use_graphs = 1 if use_graphs else 0
         self.params = default_params(**params)
         h = ctypes.c_void_p()
         _check(lib().higs_server_create(device, ctypes.byref(self.params), ctypes.byref(cfg), ctypes.byref(h)),
@@ -440,16 +460,21 @@ class Server:
         except Exception:
             pass
 
-    def add_scene(self, scene_id: int, tensors):
+    def add_scene(self, scene_id: int, tensors, stream=None):
+        """Registers a resident scene; frames of it wait for the work enqueued
+        so far on `stream` (default: torch's current stream)."""
         means, scales, quats, opac, sh = tensors
         self._keep.append(tensors)
         _check(lib().higs_server_add_scene(self._h, int(scene_id), int(means.shape[0]), _ptr(means), _ptr(scales),
-                                           _ptr(quats), _ptr(opac), _ptr(sh)), "higs_server_add_scene")
+                                           _ptr(quats), _ptr(opac), _ptr(sh), _dep_stream(stream)),
+               "higs_server_add_scene")
 
-    def submit(self, request_id: int, scene_id: int, cls: int, cam, image):
+    def submit(self, request_id: int, scene_id: int, cls: int, cam, image, stream=None):
+        """Queues a request; its frame waits for the work enqueued so far on
+        `stream` (default: torch's current stream), e.g. what last used image."""
         c = camera_c(cam)
         _check(lib().higs_server_submit(self._h, int(request_id), int(scene_id), int(cls), ctypes.byref(c),
-                                        _ptr(image)), "higs_server_submit")
+                                        _ptr(image), _dep_stream(stream)), "higs_server_submit")
 
     def poll(self):
         """Retires finished frames and admits queued ones; returns a list of
@@ -458,6 +483,19 @@ class Server:
         if n < 0:
             raise HigsError(n, "higs_server_poll")
         return [(d.request_id, d.gpu_ms, d.overflow, d.cls) for d in self._done[:n]]
+
+    def tune(self, cls: int, scene_id: int, cams, frames: int = 64, allow_batch_cap: bool = False) -> TuneReport:
+        """higs_server_tune: measures views per frame (and B_r) for class cls
+        and keeps the fastest."""
+        arr = (CameraC * len(cams))(*[camera_c(c) for c in cams])
+        rep = TuneReport()
+        _check(lib().higs_server_tune(self._h, int(cls), int(scene_id), len(cams), arr, int(frames),
+                                      1 if allow_batch_cap else 0, ctypes.byref(rep)), "higs_server_tune")
+        return rep
+
+    def set_class(self, cls: int, views_per_frame: int, batch_cap: int = 1024):
+        _check(lib().higs_server_set_class(self._h, int(cls), int(views_per_frame), int(batch_cap)),
+               "higs_server_set_class")
 
     def stats(self) -> ServerStats:
         st = ServerStats()

@@ -117,7 +117,8 @@ def run_frames(scene, cams, max_pairs, max_batches, sort_mode=1, batch_cap=1024,
         lines = open(os.path.join(out, "counts.txt")).read().split("\n")
         for k, c in enumerate(cams):
             fr = Frame()
-            rc, vis, pairs, batches, evals, ovf = (int(x) for x in lines[k].split())
+            rc, vis, pairs, batches, evals, ovf, graphs = (int(x) for x in lines[k].split())
+            fr.graphs = graphs
             fr.rc, fr.n_visible, fr.n_pairs, fr.n_batches, fr.overflow = rc, vis, pairs, batches, ovf
             fr.n_evaluations = evals
             fr.packed = packed

@@ -558,10 +558,71 @@ inline hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) {
   if (n) memcpy(d, s, n);
   return hipSuccess;
 }
-inline hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind k, hipStream_t = nullptr) {
+// Graph capture: work enqueued on a capturing stream is recorded (arguments
+// by value, copies read their source at replay) and runs at hipGraphLaunch.
+struct cpuhip_graph {
+  std::vector<std::function<void()>> ops;
+};
+typedef cpuhip_graph* hipGraph_t;
+typedef struct cpuhip_graph_exec {
+  std::vector<std::function<void()>> ops;
+}* hipGraphExec_t;
+typedef void* hipGraphNode_t;
+enum hipStreamCaptureMode {
+  hipStreamCaptureModeGlobal = 0,
+  hipStreamCaptureModeThreadLocal = 1,
+  hipStreamCaptureModeRelaxed = 2
+};
+namespace cpuhip {
+inline std::map<const void*, cpuhip_graph*>& captures() {
+  static std::map<const void*, cpuhip_graph*> m;
+  return m;
+}
+inline cpuhip_graph* capturing(const void* s) {
+  auto it = captures().find(s);
+  return it == captures().end() ? nullptr : it->second;
+}
+}  // namespace cpuhip
+inline hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode) {
+  if (!s || cpuhip::capturing(s)) return hipErrorInvalidValue;
+  cpuhip::captures()[s] = new cpuhip_graph();
+  return hipSuccess;
+}
+inline hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t* g) {
+  cpuhip_graph* c = cpuhip::capturing(s);
+  if (!c) return hipErrorInvalidValue;
+  cpuhip::captures().erase(s);
+  *g = c;
+  return hipSuccess;
+}
+inline hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, hipGraphNode_t*, char*, size_t) {
+  *e = new cpuhip_graph_exec{g->ops};
+  return hipSuccess;
+}
+inline hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t) {
+  for (auto& op : e->ops) op();
+  return hipSuccess;
+}
+inline hipError_t hipGraphDestroy(hipGraph_t g) {
+  delete g;
+  return hipSuccess;
+}
+inline hipError_t hipGraphExecDestroy(hipGraphExec_t e) {
+  delete e;
+  return hipSuccess;
+}
+inline hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind k, hipStream_t st = nullptr) {
+  if (cpuhip_graph* g = cpuhip::capturing(st)) {
+    g->ops.push_back([=] { hipMemcpy(d, s, n, k); });
+    return hipSuccess;
+  }
   return hipMemcpy(d, s, n, k);
 }
-inline hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t = nullptr) {
+inline hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t st = nullptr) {
+  if (cpuhip::capturing(st)) {  // a memset node in a graph: never recorded by the library
+    fprintf(stderr, "cpuhip: hipMemsetAsync on a capturing stream\n");
+    abort();
+  }
   if (n) memset(d, v, n);
   return hipSuccess;
 }
@@ -587,7 +648,11 @@ inline hipError_t hipEventDestroy(hipEvent_t e) {
   delete e;
   return hipSuccess;
 }
-inline hipError_t hipEventRecord(hipEvent_t e, hipStream_t = nullptr) {
+inline hipError_t hipEventRecord(hipEvent_t e, hipStream_t st = nullptr) {
+  if (cpuhip::capturing(st)) {  // the library records no events inside a graph
+    fprintf(stderr, "cpuhip: hipEventRecord on a capturing stream\n");
+    abort();
+  }
   e->t = cpuhip::now_ms();
   return hipSuccess;
 }
@@ -626,5 +691,15 @@ inline hipError_t hipGetSymbolAddress(void** p, const void* sym) {
   return hipSuccess;
 }
 
+namespace cpuhip {
+template <class... A, class... P>
+void launch_on(const void* stream, void (*k)(P...), dim3 grid, dim3 block, size_t shmem, A... args) {
+  if (cpuhip_graph* g = capturing(stream)) {
+    g->ops.push_back([=] { launch(k, grid, block, shmem, args...); });
+    return;
+  }
+  launch(k, grid, block, shmem, args...);
+}
+}  // namespace cpuhip
 #define hipLaunchKernelGGL(k, grid, block, shmem, stream, ...) \
-  cpuhip::launch((k), dim3(grid), dim3(block), (size_t)(shmem), ##__VA_ARGS__)
+  cpuhip::launch_on((const void*)(stream), (k), dim3(grid), dim3(block), (size_t)(shmem), ##__VA_ARGS__)

@@ -118,3 +118,39 @@ def test_views_in_one_frame_match_their_single_frames(precision):
     assert multi[0].n_pairs == sum(f.n_pairs for f in single)
     for a, b in zip(single, multi):
         assert np.array_equal(a.image, b.image) and np.array_equal(a.T, b.T)
+
+
+def test_graph_replay_matches_kernel_by_kernel_frames():
+    """params.use_graphs: frames recorded into graphs and replayed (a shape
+    seen before replays its graph with a new camera and scene size inside the
+    same padded range) give the images of the kernel-by-kernel frames, bit for
+    bit; so does a several-view frame replayed after a first frame of the same
+    shape with other cameras and outputs."""
+    cpu = _cpu()
+    sc = scenes.clustered_scene(6000, seed=6, n_clusters=4)
+    cams = scenes.orbit_cameras(5, 3, 160, 96, 140.0)[:4]
+    uses = [6000, 5800, 6000, 3000]   # frames 0-2 share one padded range, 3 another
+    eager = cpu.run_frames(sc, cams, max_pairs=1 << 17, max_batches=1 << 12, uses=uses)
+    graph = cpu.run_frames(sc, cams, max_pairs=1 << 17, max_batches=1 << 12, uses=uses, entry=3)
+    assert [f.graphs for f in graph] == [1, 1, 1, 2]
+    for a, b in zip(eager, graph):
+        assert a.rc == 0 and b.rc == 0 and b.overflow == 0 and b.n_pairs == a.n_pairs
+        assert np.array_equal(a.image, b.image) and np.array_equal(a.T, b.T)
+    views = cpu.run_frames(sc, cams[:3], max_pairs=1 << 17, max_batches=1 << 12, uses=uses[:3], entry=4)
+    assert views[0].graphs == 1
+    for a, b in zip(eager[:3], views):
+        assert b.rc == 0 and np.array_equal(a.image, b.image) and np.array_equal(a.T, b.T)
+
+
+def test_server_frames_hold_several_requests():
+    """The render server with several requests per frame and graph replay:
+    every request's image is the kernel-by-kernel frame's, bit for bit, in two
+    rounds (the second replays the graph on the same context)."""
+    cpu = _cpu()
+    sc = scenes.clustered_scene(6000, seed=6, n_clusters=4)
+    cams = scenes.orbit_cameras(5, 3, 160, 96, 140.0)[:3]
+    uses = [6000, 4000, 6000]
+    eager = cpu.run_frames(sc, cams, max_pairs=1 << 16, max_batches=1 << 12, uses=uses)
+    served = cpu.run_frames(sc, cams, max_pairs=1 << 16, max_batches=1 << 12, uses=uses, entry=5)
+    for a, b in zip(eager, served):
+        assert b.rc == 0 and np.array_equal(a.image, b.image)

@@ -1,13 +1,14 @@
 """The render server (higs_server_*): continuous batching of frame requests
-over contexts and streams within an HBM budget.
+over contexts and streams within an HBM arena, several requests per frame.
 
-CPU: the context footprint the admission budget is counted in (host-only
-arithmetic) against the sizes of the arrays a context holds; the request
-trace generator.  GPU: every request's image in a mixed burst (several
-scenes and resolutions, frames overlapping on the device) equals the image
+CPU: the context footprint (host-only arithmetic) against the sizes of the
+arrays a context holds; the request trace generator.  GPU: every request's
+image in a mixed burst (several scenes and resolutions, frames overlapping on
+the device, several requests per frame, graph replay) equals the image
 rendered alone on a fresh context, bit for bit; so does the plain
-one-frame-at-a-time mode; a budget too small for all classes at once still
-serves every request, by releasing idle contexts."""
+one-frame-at-a-time mode; an arena too small for all classes at once still
+serves every request, by releasing idle contexts; the autotuner's choice
+serves the same images; a served frame matches the oracle."""
 import numpy as np
 import pytest
 
@@ -63,12 +64,14 @@ def _burst(n_req, seed=3):
     return reqs
 
 
-def _serve(tens, reqs, budget, max_in_flight, max_g):
+def _serve(tens, reqs, budget, max_in_flight, max_g, views=None, graphs=False, tune=None):
     import torch
     srv = higs.Server([(w, h, 4 * max_g) for w, h in SMALL], max_gaussians=max_g, hbm_budget=budget,
-                      max_in_flight=max_in_flight)
+                      max_in_flight=max_in_flight, views_per_frame=views, use_graphs=graphs)
     for k, t in enumerate(tens):
         srv.add_scene(k, t)
+    if tune:
+        tune(srv)
     images = {}
     for rid, sc, cls, cam in reqs:
         images[rid] = torch.full((cam.height, cam.width, 3), -1.0, device="cuda")
@@ -85,18 +88,22 @@ def _serve(tens, reqs, budget, max_in_flight, max_g):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("max_in_flight", [6, 1])
-def test_alone_equals_in_mix(max_in_flight):
+@pytest.mark.parametrize("max_in_flight,views,graphs", [(6, None, False), (1, None, False), (4, (4, 3, 2), True),
+                                                        (3, (8, 8, 8), False)])
+def test_alone_equals_in_mix(max_in_flight, views, graphs):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     sc = [scenes.clustered_scene(n, seed=50 + k, n_clusters=12) for k, n in enumerate((20_000, 40_000, 80_000))]
     tens = [higs.scene_tensors(s) for s in sc]
     reqs = _burst(36)
-    images, done, st = _serve(tens, reqs, budget=1 << 40, max_in_flight=max_in_flight, max_g=80_000)
+    images, done, st = _serve(tens, reqs, budget=4 << 30, max_in_flight=max_in_flight, max_g=80_000,
+                              views=views, graphs=graphs)
     assert len(done) == len(reqs) and all(ovf == 0 for _, ovf in done.values())
     assert all(ms > 0 for ms, _ in done.values())
     assert st.queued == 0 and st.in_flight == 0 and st.completed == len(reqs)
+    if views:
+        assert st.frames < len(reqs)      # requests shared frames
     ctx = higs.Context(80_000, 640, 360, max_pairs=4 * 80_000)
     for rid, s, cls, cam in reqs:
         alone, _ = higs.render(ctx, tens[s], cam, with_T=False)
@@ -139,3 +146,113 @@ def test_submit_checks_the_class_size():
     with pytest.raises(higs.HigsError):
         srv.submit(1, 7, 0, scenes.camera_at_origin(64, 64, 64.0), img)   # unknown scene
     srv.close()
+
+
+@pytest.mark.gpu
+def test_tuned_server_serves_the_same_images():
+    """higs_server_tune measures views per frame for a class and keeps the
+    fastest; the server then still serves every request's alone image."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sc = [scenes.clustered_scene(n, seed=70 + k, n_clusters=12) for k, n in enumerate((20_000, 40_000, 60_000))]
+    tens = [higs.scene_tensors(s) for s in sc]
+    reqs = _burst(30, seed=11)
+    reports = []
+
+    def tune(srv):
+        for cls, (w, h) in enumerate(SMALL):
+            cams = [c for _, _, k, c in _burst(40, seed=12) if k == cls][:6]
+            rep = srv.tune(cls, 2, cams, frames=12)
+            assert 1 <= rep.n_trials <= higs.TUNE_MAX_TRIALS
+            trials = {rep.trial_views[t]: rep.trial_fps[t] for t in range(rep.n_trials)}
+            assert rep.views_per_frame in trials and trials[rep.views_per_frame] == max(trials.values())
+            assert rep.batch_cap == 1024
+            reports.append(rep)
+        st = srv.stats()
+        assert [st.views_per_frame[c] for c in range(3)] == [r.views_per_frame for r in reports]
+
+    images, done, st = _serve(tens, reqs, budget=2 << 30, max_in_flight=4, max_g=60_000, graphs=True, tune=tune)
+    assert len(done) == len(reqs) and all(ovf == 0 for _, ovf in done.values())
+    ctx = higs.Context(60_000, 640, 360, max_pairs=4 * 60_000)
+    for rid, s, cls, cam in reqs:
+        alone, _ = higs.render(ctx, tens[s], cam, with_T=False)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, images[rid]), rid
+
+
+@pytest.mark.gpu
+def test_frames_wait_for_the_callers_stream():
+    """A request's frame is ordered after the work the caller enqueued on its
+    stream before submitting: images filled on a side stream just before the
+    submit end up rendered, not filled."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sc = scenes.clustered_scene(40_000, seed=81, n_clusters=8)
+    t = higs.scene_tensors(sc)
+    reqs = _burst(12, seed=13)
+    srv = higs.Server([(w, h, 4 * sc.n) for w, h in SMALL], max_gaussians=sc.n, hbm_budget=1 << 30,
+                      max_in_flight=4, views_per_frame=(3, 3, 3))
+    side = torch.cuda.Stream()
+    srv.add_scene(0, t)
+    images = {}
+    with torch.cuda.stream(side):
+        for rid, _, cls, cam in reqs:
+            images[rid] = torch.empty((cam.height, cam.width, 3), device="cuda")
+            big = torch.randn(4096, 4096, device="cuda")
+            for _ in range(4):                      # keep the side stream busy
+                big = big @ big.T.contiguous() / 4096.0
+            images[rid].fill_(-1.0)
+            srv.submit(rid, 0, cls, cam, images[rid])  # torch's current stream: `side`
+    got = 0
+    for _ in range(200000):
+        got += len(srv.poll())
+        if got == len(reqs):
+            break
+    srv.close()
+    torch.cuda.synchronize()
+    assert got == len(reqs)
+    ctx = higs.Context(sc.n, 640, 360, max_pairs=4 * sc.n)
+    for rid, _, cls, cam in reqs:
+        alone, _ = higs.render(ctx, t, cam, with_T=False)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, images[rid]), rid
+
+
+@pytest.mark.gpu
+def test_a_served_frame_matches_the_oracle(orc):
+    """One request served inside a frame of three (graph replay) against the
+    oracle's frame of its camera, on every 8th pixel row, at the parity
+    tolerance."""
+    import torch
+    from tests import gpu_common as gc
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sc = scenes.clustered_scene(100_000, seed=82, n_clusters=10)
+    t = higs.scene_tensors(sc)
+    cams = scenes.orbit_cameras(3, 17, 640, 360, 380.0)
+    srv = higs.Server([(640, 360, 8 * sc.n)], max_gaussians=sc.n, hbm_budget=1 << 30, max_in_flight=2,
+                      views_per_frame=(3,), use_graphs=True)
+    srv.add_scene(0, t)
+    imgs = [torch.empty((360, 640, 3), device="cuda") for _ in cams]
+    for k, cam in enumerate(cams):
+        srv.submit(k, 0, 0, cam, imgs[k])
+    done = []
+    for _ in range(200000):
+        done += srv.poll()
+        if len(done) == len(cams):
+            break
+    st = srv.stats()
+    srv.close()
+    assert len(done) == 3 and st.frames == 1 and all(d[2] == 0 for d in done)
+    cam = cams[2]
+    fr = orc.frame(sc, cam, render=False)
+    ys = np.arange(0, cam.height, 8)
+    pix = np.stack(np.meshgrid(np.arange(cam.width), ys), -1).reshape(-1, 2)
+    img_o, _, amb = orc.render_tiled(fr.geo, fr.sorted_gid, fr.mt_off, fr.batch_tab, cam, pixels=pix)
+    g = imgs[2].cpu().numpy()[pix[:, 1], pix[:, 0]].astype(np.float64)
+    ok = amb == 0
+    assert (~ok).mean() <= gc.AMB_MAX_FRACTION
+    d = np.abs(g - img_o)
+    assert d[ok].max() <= gc.IMG_MAX_ABS and d.mean() <= gc.IMG_MEAN_ABS
