@@ -58,14 +58,14 @@ COPY_CALIBRATION_BYTES = 1 << 30
 MEASURED_TRAFFIC = {
     # profiles/frame_1080p_5p8m_hbm_traffic.md (sort: histogram + plan + every
     # onesweep dispatch of a frame)
-    "raster": {"src_sha256": "724d956896ea5bb85d9e407b44a58382ceccde693cd192802fa38f80c997697c",
-              "bytes_per_launch": 1512400000},
-    "project": {"src_sha256": "48cfee213d0d1466f6388dd8aaa1b31ebdd0dff844796802d96498c54dad2bfa",
+    "raster": {"src_sha256": "d9c90ca20034df1bc90d490c88d68b808da1df735d69df2d6524077c1cb4d749",
+              "bytes_per_launch": 1512700000},
+    "project": {"src_sha256": "e27d24c32e11897753cc746c395fb5144a931e058f2e90c03f33b2ded0ba0531",
                "bytes_per_launch": 1714600000},
-    "fill": {"src_sha256": "95c563041c3f244863417a23f709a99ab5ff86b18ffad3b356695d4ca31938b8",
+    "fill": {"src_sha256": "061ea1a1b8a4b96d473708182d9973f340feff7cdcae2d9387889c58b1d92e06",
             "bytes_per_launch": 134900000},
-    "sort": {"src_sha256": "d19c0c33859fee1d5b0994afbaa4403bf3e924b751f6fce897d7cdd051e942df",
-            "bytes_per_launch": 914500000},
+    "sort": {"src_sha256": "79580a88de2d51b0305de205097c254f9d8504992e15945cb73da68b77bdbccc",
+            "bytes_per_launch": 915800000},
 }
 # the sources each figure depends on (the shared header holds the kernels' shapes)
 KERNEL_SOURCES = {"project": ("project.hip", "predicate.h", "higs_internal.h"),
@@ -390,6 +390,38 @@ def protocol_median(ctx, tens, cams, image, iters=10):
     return float(np.median(ms)), per_view
 
 
+def leg_graph_replay(scene, tens, cams, max_pairs, max_batches, steps=120, warmup=10):
+    """The main workload with every frame replayed from a HIP graph (one
+    launch per frame, on a stream of its own, no kernel timers): frames per
+    second of `steps` frames over the orbit, and whether view 0's image is the
+    kernel-by-kernel one bit for bit."""
+    import torch
+    from paper_2606_00352_amd import higs
+    side = torch.cuda.Stream()
+    g = higs.Context(scene.n, 1920, 1080, max_pairs=max_pairs, max_batches=max_batches, use_graphs=1)
+    e = higs.Context(scene.n, 1920, 1080, max_pairs=max_pairs, max_batches=max_batches)
+    image = torch.empty((1080, 1920, 3), dtype=torch.float32, device="cuda:0")
+    ref = torch.empty_like(image)
+    torch.cuda.synchronize()
+    for i in range(warmup):
+        g.render(*tens, cams[i % len(cams)], image, stream=side)
+    side.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        g.render(*tens, cams[i % len(cams)], image, stream=side)
+    side.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    g.render(*tens, cams[0], image, stream=side)
+    side.synchronize()
+    e.render(*tens, cams[0], ref)
+    torch.cuda.synchronize()
+    out = {"fps": round(1000.0 / ms, 2), "ms_per_frame": round(ms, 4), "graphs": int(g.counts().graphs),
+           "equals_kernel_by_kernel": bool(torch.equal(image, ref))}
+    g.close()
+    e.close()
+    return out
+
+
 def leg_reduced(scene, tens, cams, steps=120, warmup=10):
     """The reduced-precision mode on the main workload: the half-precision
     raster, alone and with the 32-byte packed SH, timed like the main loop;
@@ -634,6 +666,9 @@ def main():
                      "unit": unit, "frac": round(ach / peak, 4),
                      "traffic": measured_traffic(traffic_key(dom, seg))},
     }
+    log("graph replay leg")
+    result["graph_replay"] = leg_graph_replay(scene, tens, cams, ctx.max_pairs, ctx.max_batches)
+    log(f"graph replay: {result['graph_replay']}")
     if not args.no_reduced:
         log("reduced-precision leg")
         ctx.close()

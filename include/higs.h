@@ -388,10 +388,13 @@ int higs_server_get_stats(higs_server* server, higs_server_stats* out);
  * views per frame in {1, 2, 4, 8, 16} (those whose context fits the arena)
  * and, with allow_batch_cap, B_r in {1024, 512, 256} (other values change the
  * batch boundaries, so images are then no longer those of B_r = 1024 bit for
- * bit); each trial keeps max_in_flight frames in flight on as many contexts as
- * fit.  The fastest (requests per second) becomes the class's setting.  The
- * server must be idle (HIGS_E_STATE otherwise); its idle contexts are
- * released.  Synchronises the device. */
+ * bit); each trial keeps up to max_in_flight frames in flight on as many
+ * contexts as the class's share of the arena (1 / n_classes) holds.  The
+ * setting with the fewest views per frame (then the largest B_r) within 3% of
+ * the fastest trial (requests per second) becomes the class's.  The server
+ * must be idle (HIGS_E_STATE otherwise); its idle contexts are released.
+ * HIGS_E_CAPACITY if no candidate's context fits the share.  Synchronises the
+ * device. */
 #define HIGS_TUNE_MAX_TRIALS 16
 typedef struct {
   int32_t views_per_frame, batch_cap;   /* chosen */

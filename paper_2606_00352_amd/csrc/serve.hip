@@ -415,8 +415,12 @@ double trial(higs_server* s, int cls, const Scene& sc, int n_cams, const higs_ca
              int views, int cap, int frames, int* rc_out) {
   *rc_out = HIGS_OK;
   const int64_t b = slot_bytes(s, cls, views, cap);
-  if (b <= 0 || (size_t)Arena::round((size_t)b) > s->arena.size) return 0.0;
-  const int k = std::max(1, std::min(s->cfg.max_in_flight, frames));
+  // serving holds contexts of every class: a trial gets the class's share of
+  // the arena, and as many contexts (up to max_in_flight) as the share holds
+  const size_t share = s->arena.size / (size_t)s->cfg.n_classes;
+  if (b <= 0 || Arena::round((size_t)b) > share) return 0.0;
+  const int k = std::max(1, std::min({s->cfg.max_in_flight, frames,
+                                      (int)(share / Arena::round((size_t)b))}));
   const size_t px = (size_t)s->cfg.width[cls] * s->cfg.height[cls] * 3;
   float* images = nullptr;
   if (hipMalloc(reinterpret_cast<void**>(&images), px * 4 * (size_t)views * k) != hipSuccess) {
@@ -663,8 +667,7 @@ int higs_server_tune(higs_server* s, int32_t cls, int32_t scene_id, int32_t n_ca
   *out = higs_tune_report{};
   static const int kViews[] = {1, 2, 4, 8, 16};
   static const int kCaps[] = {1024, 512, 256};
-  double best = -1.0;
-  int best_v = s->views[cls], best_c = s->batch_cap[cls];
+  double fps_of[HIGS_TUNE_MAX_TRIALS];
   for (int ci = 0; ci < (allow_batch_cap ? 3 : 1); ++ci) {
     const int cap = allow_batch_cap ? kCaps[ci] : s->params.batch_cap;
     for (int v : kViews) {
@@ -677,11 +680,21 @@ int higs_server_tune(higs_server* s, int32_t cls, int32_t scene_id, int32_t n_ca
       out->trial_views[t] = v;
       out->trial_batch_cap[t] = cap;
       out->trial_fps[t] = (float)fps;
-      if (fps > best) {
-        best = fps;
-        best_v = v;
-        best_c = cap;
-      }
+      fps_of[t] = fps;
+    }
+  }
+  if (out->n_trials == 0) return HIGS_E_CAPACITY;  // no candidate fits the arena
+  // the fewest views per frame (then the largest B_r) within 3% of the
+  // fastest trial: grouping adds latency, and closer figures are noise
+  double top = 0.0;
+  for (int t = 0; t < out->n_trials; ++t) top = std::max(top, fps_of[t]);
+  int best_v = 0, best_c = 0;
+  for (int t = 0; t < out->n_trials; ++t) {
+    if (fps_of[t] < 0.97 * top) continue;
+    const int v = out->trial_views[t], c = out->trial_batch_cap[t];
+    if (!best_v || v < best_v || (v == best_v && c > best_c)) {
+      best_v = v;
+      best_c = c;
     }
   }
   s->views[cls] = best_v;

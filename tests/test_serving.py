@@ -166,7 +166,9 @@ def test_tuned_server_serves_the_same_images():
             rep = srv.tune(cls, 2, cams, frames=12)
             assert 1 <= rep.n_trials <= higs.TUNE_MAX_TRIALS
             trials = {rep.trial_views[t]: rep.trial_fps[t] for t in range(rep.n_trials)}
-            assert rep.views_per_frame in trials and trials[rep.views_per_frame] == max(trials.values())
+            top = max(trials.values())
+            assert rep.views_per_frame in trials and trials[rep.views_per_frame] >= 0.97 * top * (1 - 1e-6)
+            assert all(v >= rep.views_per_frame for v, f in trials.items() if f >= 0.97 * top * (1 + 1e-6))
             assert rep.batch_cap == 1024
             reports.append(rep)
         st = srv.stats()
