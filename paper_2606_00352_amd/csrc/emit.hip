@@ -25,15 +25,13 @@
 
 namespace higs {
 
-__global__ void clear_kernel(DeviceCounters* dc, uint32_t* hist, int n_hist, uint32_t* seg_count,
-                             int n_seg) {
+__global__ void clear_kernel(DeviceCounters* dc, uint32_t* hist, int n_hist) {
   uint32_t* w = reinterpret_cast<uint32_t*>(dc);
   const int nw = (int)(sizeof(DeviceCounters) / 4);
   const int keep = (int)(offsetof(DeviceCounters, epoch) / 4);
   for (int k = threadIdx.x; k < nw; k += blockDim.x)
     if (k != keep) w[k] = 0;
   for (int k = threadIdx.x; k < n_hist; k += blockDim.x) hist[k] = 0;
-  for (int k = threadIdx.x; k < n_seg; k += blockDim.x) seg_count[k] = 0;
   __syncthreads();
   if (threadIdx.x == 0) {
     dc->key_min = 0xffffffffu;
@@ -42,9 +40,8 @@ __global__ void clear_kernel(DeviceCounters* dc, uint32_t* hist, int n_hist, uin
   }
 }
 
-hipError_t launch_clear(DeviceCounters* dc, uint32_t* hist, int n_hist, uint32_t* seg_count,
-                        int n_seg, hipStream_t s) {
-  hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(1024), 0, s, dc, hist, n_hist, seg_count, n_seg);
+hipError_t launch_clear(DeviceCounters* dc, uint32_t* hist, int n_hist, hipStream_t s) {
+  hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(1024), 0, s, dc, hist, n_hist);
   return hipGetLastError();
 }
 

@@ -45,8 +45,8 @@ struct higs_ctx {
   float4* partials = nullptr;
   DeviceCounters* dc = nullptr;
   // segmented sort: per macro-tile counts, fill cursors, chunk and block tables
-  uint32_t *seg_count = nullptr, *seg_cursor = nullptr, *seg_chunk_off = nullptr,
-           *seg_blk_off = nullptr;
+  uint16_t* seg_cm = nullptr;  // [n_mt][n_b] count matrix
+  uint32_t *seg_off = nullptr, *seg_tiles = nullptr, *seg_list = nullptr;
   bool segmented() const { return params.sort_mode == HIGS_SORT_SEGMENTED; }
   // adjoint buffers, allocated by the first higs_raster_backward
   float2* bwd_state = nullptr;  // [max_batches][32 tiles][64 px]: T before, suffix X
@@ -169,8 +169,8 @@ void free_all(higs_ctx* c) {
     void* bufs[] = {c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau, c->f_key, c->f_cnt,
                     c->f_span, c->rec, c->block_sums, c->keys[0], c->keys[1], c->vals[0],
                     c->vals[1], c->hist, c->plan, c->status, c->mt_off, c->batch_first,
-                    c->batch_tab, c->active, c->partials, c->dc, c->seg_count, c->seg_cursor,
-                    c->seg_chunk_off, c->seg_blk_off, c->view_table};
+                    c->batch_tab, c->active, c->partials, c->dc, c->seg_cm, c->seg_off,
+                    c->seg_tiles, c->seg_list, c->view_table};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
   }
@@ -225,10 +225,15 @@ void for_each_buffer(higs_ctx* c, F&& f) {
   f(&c->active, B);
   f(&c->partials, B * kTilesPerMt * 64);
   f(&c->dc, (size_t)1);
-  f(&c->seg_count, mt);
-  f(&c->seg_cursor, mt);
-  f(&c->seg_chunk_off, mt + 1);
-  f(&c->seg_blk_off, mt + 1);
+  // segmented sort (single-view contexts only): the (macro-tile, partition
+  // batch) count matrix and its scan, the tile sums, the tier lists
+  const size_t mat = c->segmented()
+                         ? mt * (size_t)((c->max_g + kSegBatch - 1) / kSegBatch)
+                         : 1;
+  f(&c->seg_cm, mat);
+  f(&c->seg_off, mat);
+  f(&c->seg_tiles, (mat + kSegScanTile - 1) / kSegScanTile + 1);
+  f(&c->seg_list, c->segmented() ? (size_t)kSegTiers * mt + mt + 1 : 1);
   f(&c->view_table, (size_t)c->params.max_views);
 }
 
@@ -406,6 +411,7 @@ int create_ctx(int device, const higs_params* params, int64_t max_gaussians, int
   (void)raster_per_cu_config();
   (void)raster16_per_cu_config();
   (void)onesweep_per_cu_config();
+  (void)seg_sort_configs();
   higs_ctx* c = new (std::nothrow) higs_ctx();
   if (!c) return HIGS_E_NOMEM;
   c->device = device;
@@ -647,8 +653,7 @@ int project_frame(higs_ctx* c, const higs_camera* cam0, hipStream_t s, bool capt
   c->views.n_pad = c->n_pad;
   c->n_virt = c->n_pad * c->n_views;
   c->n_passes = (32 + n_bits((uint32_t)(c->n_mt_all - 1)) + kRadixBits - 1) / kRadixBits;
-  int rc = hip_err(launch_clear(c->dc, c->hist, kMaxPasses * kRadix, c->seg_count,
-                                c->segmented() ? c->n_mt : 0, s));
+  int rc = hip_err(launch_clear(c->dc, c->hist, kMaxPasses * kRadix, s));
   if (rc) return rc;
   {
     TimerScope ts(c, HIGS_TIMER_PROJECT, s);
@@ -704,11 +709,11 @@ int higs_project(higs_ctx* c, int64_t n, const float* means, const float* scales
 namespace {
 SegBuffers seg_buffers(higs_ctx* c) {
   SegBuffers sb;
-  sb.seg_count = c->seg_count;
-  sb.cursor = c->seg_cursor;
+  sb.cm = c->seg_cm;
+  sb.tile_sum = c->seg_tiles;
+  sb.off = c->seg_off;
+  sb.list = c->seg_list;
   sb.mt_off = c->mt_off;
-  sb.chunk_off = c->seg_chunk_off;
-  sb.blk_off = c->seg_blk_off;
   sb.comp = c->keys[0];
   sb.runs = c->keys[1];
   sb.ids = c->vals[0];

@@ -42,6 +42,13 @@ constexpr int kMaxPasses = 8;
 // Segmented sort geometry.
 constexpr int kSegBatch = 8192;     // B_p, gaussians per partition batch (sec. 4.3)
 constexpr int kSegMaxLevels = 20;   // merge levels of the largest possible segment
+constexpr int kSegScanTile = 4096;  // count-matrix entries per scan tile
+// Segment sort tiers (sec. 4.4): segments of up to 1,024, 2,048, 4,096 and
+// 8,192 pairs, each sorted whole by one workgroup in LDS, and longer ones,
+// cut into 8,192-pair chunks (sorted the same way) and merged.
+constexpr int kSegTiers = 5;
+constexpr uint32_t kSegTierCap[4] = {1024, 2048, 4096, 8192};
+constexpr int kSegChunk = 8192;     // pairs of a chunk of a long segment
 constexpr int kSegMaxMt = 20480;    // macro-tiles whose two LDS tables fit 160 KiB
 
 // Raster record written by the projection for every visible gaussian and
@@ -76,7 +83,10 @@ struct DeviceCounters {
   uint32_t key_max;         //   frame's visible gaussians (key compression)
   uint32_t bwd_next;        // work counter of the persistent raster adjoint
   uint32_t seg_max;         // largest segment (segmented sort)
-  uint32_t seg_next[1 + 20];  // work counters: chunk sort, then one per merge level
+  uint32_t seg_next[kSegTiers + kSegMaxLevels];  // work counters: the tiers' sorts, then
+                                                 //   one per merge level
+  uint32_t seg_tier_n[kSegTiers];  // segments in each tier (tier 3: long segments)
+  uint32_t seg_chunks;      // chunks of the long segments
   uint32_t id_shift;        // > 0: each pair is one word key << id_shift | id (see scan_kernel)
   uint32_t sort_last;       // last radix pass that moves data (it writes the id array)
   uint32_t pad[6];
@@ -148,8 +158,7 @@ struct Views {
 };
 
 // ---- host-side launchers (one translation unit each) ----------------------
-hipError_t launch_clear(DeviceCounters* dc, uint32_t* hist, int n_hist, uint32_t* seg_count,
-                        int n_seg, hipStream_t s);
+hipError_t launch_clear(DeviceCounters* dc, uint32_t* hist, int n_hist, hipStream_t s);
 
 hipError_t launch_project(const Views& views, CamArgs shape, ParamArgs prm, float* f_mx,
                           float* f_my, float* f_a, float* f_b, float* f_c, float* f_tau,
@@ -215,11 +224,11 @@ hipError_t launch_backward(int64_t n, const float* means, const float* scales, c
                            hipStream_t s);
 
 struct SegBuffers {
-  uint32_t* seg_count;  // [n_mt] pairs per macro-tile
-  uint32_t* cursor;     // [n_mt] fill cursors
+  uint16_t* cm;         // [n_mt][n_b] pairs per (macro-tile, partition batch)
+  uint32_t* tile_sum;   // [tiles + 1] scan tile sums, then their exclusive scan
+  uint32_t* off;        // [n_mt][n_b] first pair slot of each (macro-tile, batch)
   uint32_t* mt_off;     // [n_mt + 1] segment offsets
-  uint32_t* chunk_off;  // [n_mt + 1] first sort chunk of each segment
-  uint32_t* blk_off;    // [n_mt + 1] first merge block of each multi-chunk segment
+  uint32_t* list;       // [4][n_mt] segments of each tier, then [n_mt + 1] chunk table
   uint64_t* comp;       // [max_pairs] composites as filled, then a merge buffer
   uint64_t* runs;       // [max_pairs] sorted runs / merge buffer
   uint32_t* ids;        // [max_pairs] output: ids in (macro-tile, depth, id) order
@@ -248,6 +257,7 @@ int raster_workers_per_cu();
 int raster_per_cu_config();
 int raster16_per_cu_config();
 int onesweep_per_cu_config();
+int seg_sort_configs();
 
 // Enqueues a copy of the context's frame counters into pinned host memory
 // (sizeof(DeviceCounters) bytes) on stream s.

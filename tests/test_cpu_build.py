@@ -154,3 +154,45 @@ def test_server_frames_hold_several_requests():
     served = cpu.run_frames(sc, cams, max_pairs=1 << 16, max_batches=1 << 12, uses=uses, entry=5)
     for a, b in zip(eager, served):
         assert b.rc == 0 and np.array_equal(a.image, b.image)
+
+
+def _dense_scene(n, w, h, f, seed, spread_x, spread_y, scale):
+    sc = scenes.uniform_scene(n, seed=seed)
+    rng = np.random.default_rng(seed)
+    z = rng.uniform(2, 6, n).astype(np.float32)
+    sc.means[:, 0] = rng.uniform(-spread_x, spread_x, n) * z / f
+    sc.means[:, 1] = rng.uniform(-spread_y, spread_y, n) * z / f
+    sc.means[:, 2] = z
+    sc.scales[:] = scale
+    return sc, scenes.camera_at_origin(w, h, f)
+
+
+@pytest.mark.parametrize("case", ["config0", "equal_depths", "dense_macro_tile", "long_segment"])
+def test_segmented_sort_matches_the_oracle(orc, case):
+    """The segmented form (count matrix, scan, fill, tiered segment sorts,
+    merges of long segments): the sorted (macro-tile, depth, id) list, the
+    segment offsets and the batches equal the oracle's, bit for bit, for
+    segments in every tier and a long one of several chunks."""
+    cpu = _cpu()
+    if case == "config0":
+        sc, cams = scenes.config0()
+        cam = cams[0]
+    elif case == "equal_depths":
+        rng = np.random.default_rng(2)
+        sc = scenes.uniform_scene(2000, seed=12)
+        sc.means[:, 2] = 3.0
+        sc.means[:, :2] = rng.uniform(-0.5, 0.5, (2000, 2))
+        cam = scenes.camera_at_origin(160, 160, 160.0)
+    elif case == "dense_macro_tile":   # ~9,000 pairs in one macro-tile: tier 2
+        sc, cam = _dense_scene(9000, 256, 128, 256.0, 21, 20, 10, 0.004)
+    else:                              # ~40,000 in one: three chunks, two merge levels
+        sc, cam = _dense_scene(40_000, 64, 32, 64.0, 21, 30, 14, 0.003)
+    fr = cpu.run_frames(sc, [cam], max_pairs=1 << 17, max_batches=4096, sort_mode=0)[0]
+    o = orc.frame(sc, cam)
+    assert fr.rc == 0 and fr.overflow == 0
+    want = (o.sorted_mt.astype(np.uint64) << np.uint64(32)) | o.sorted_key.astype(np.uint64)
+    assert np.array_equal(fr.keys, want)
+    assert np.array_equal(fr.ids, o.sorted_gid.astype(np.uint32))
+    assert np.array_equal(fr.batches.astype(np.int64), o.batch_tab.astype(np.int64))
+    if case == "long_segment":
+        assert fr.n_pairs > 32768

@@ -236,11 +236,11 @@ def test_untiled_definition_within_eps(orc):
 
 
 @SORT_MODES
-def test_one_segment_of_forty_thousand(orc, sort_mode):
-    """40,000 gaussians in one 64x32 macro-tile: a segment of five 8,192-key
+def test_one_segment_of_seventy_thousand(orc, sort_mode):
+    """70,000 gaussians in one 64x32 macro-tile: a segment of five 16,384-pair
     chunks, merged over three levels (an odd run at each) in the segmented
     sort."""
-    n = 40_000
+    n = 70_000
     sc = scenes.uniform_scene(n, seed=21)
     rng = np.random.default_rng(21)
     z = rng.uniform(2, 6, n).astype(np.float32)
@@ -250,7 +250,7 @@ def test_one_segment_of_forty_thousand(orc, sort_mode):
     sc.scales[:] = 0.003
     cam = scenes.camera_at_origin(64, 32, 64.0)
     ctx, _ = _full_check(orc, sc, cam, sort_mode=sort_mode, check_partials=False)
-    assert ctx.counts().n_pairs > 32768
+    assert ctx.counts().n_pairs > 4 * 16384
 
 
 def test_sort_modes_give_identical_frames(orc):

@@ -33,7 +33,7 @@ def test_context_footprint_counts_every_array():
     assert higs.ctx_footprint(0, P, B, W, H) == higs.E_INVALID
     # four views per frame: four ranges of gaussians and of macro-tiles
     four = higs.ctx_footprint(G, P, B, W, H, max_views=4)
-    grow = 3 * (G * (9 * 4 + 48) + 2 * nblk * 4 + 6 * n_mt * 4)
+    grow = 3 * (G * (9 * 4 + 48) + 2 * nblk * 4 + 2 * n_mt * 4)
     assert 0 < four - got - grow <= 3 * 256
 
 
