@@ -58,14 +58,14 @@ COPY_CALIBRATION_BYTES = 1 << 30
 MEASURED_TRAFFIC = {
     # profiles/frame_1080p_5p8m_hbm_traffic.md (sort: histogram + plan + every
     # onesweep dispatch of a frame)
-    "raster": {"src_sha256": "d9c90ca20034df1bc90d490c88d68b808da1df735d69df2d6524077c1cb4d749",
+    "raster": {"src_sha256": "d6ee59bc9dc078f1e13491729718a41114e58a5831f0d5195c1254859cf4fe93",
               "bytes_per_launch": 1512700000},
-    "project": {"src_sha256": "e27d24c32e11897753cc746c395fb5144a931e058f2e90c03f33b2ded0ba0531",
+    "project": {"src_sha256": "357ac9a015e703306b4f12091518cd4c3dcb34d9d444167b9fa16e487d983bcb",
                "bytes_per_launch": 1714600000},
-    "fill": {"src_sha256": "061ea1a1b8a4b96d473708182d9973f340feff7cdcae2d9387889c58b1d92e06",
+    "fill": {"src_sha256": "9cd21f5624bf6fad1305ea6288642896badc22f0ec673c777d6da56b7278d656",
             "bytes_per_launch": 134900000},
-    "sort": {"src_sha256": "79580a88de2d51b0305de205097c254f9d8504992e15945cb73da68b77bdbccc",
-            "bytes_per_launch": 915800000},
+    "sort": {"src_sha256": "fa5fdd3a4ee1b28ece04269d3037d5be19b4028359339b47912b6192762055ba",
+            "bytes_per_launch": 919000000},
 }
 # the sources each figure depends on (the shared header holds the kernels' shapes)
 KERNEL_SOURCES = {"project": ("project.hip", "predicate.h", "higs_internal.h"),
