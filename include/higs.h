@@ -93,6 +93,11 @@ typedef struct {
   int32_t sh_format;  /* HIGS_SH_FLOAT32 (default) or HIGS_SH_PACKED32 */
   int32_t max_views;  /* views one frame of higs_render_views may hold, 1..HIGS_MAX_VIEWS (1) */
   int32_t use_graphs; /* 1: replay frames from HIP graphs (see below); 0 (default): launch each kernel */
+  int32_t raster_chain; /* batches of one macro-tile that a raster workgroup takes in order,
+                           1..64 (64): within them it leaves out a render tile once the product
+                           of the earlier batches' transmittances is below t_eps at all 64 of
+                           its pixels, where the merge of Eq. 1 stops reading; 1: every
+                           (macro-tile, batch) unit is rasterised in full */
 } higs_params;
 
 #define HIGS_MAX_VIEWS 64

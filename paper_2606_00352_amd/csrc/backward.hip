@@ -123,9 +123,9 @@ __device__ __forceinline__ int wave_max_int(int v) {
 __global__ void __launch_bounds__(kRasterBwdThreads)
 raster_backward_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ vals0,
                        const uint32_t* __restrict__ vals1, const RasterRecord* __restrict__ rec,
-                       const uint32_t* __restrict__ batch_tab, DeviceCounters* __restrict__ dc,
-                       const float2* __restrict__ state, const float* __restrict__ dimg,
-                       float* __restrict__ dgeo) {
+                       const uint32_t* __restrict__ batch_tab, const uint32_t* __restrict__ active,
+                       DeviceCounters* __restrict__ dc, const float2* __restrict__ state,
+                       const float* __restrict__ dimg, float* __restrict__ dgeo) {
   __shared__ RasterLds L;
   if (dc->overflow) return;  // the frame stopped at a capacity overflow
   const uint32_t* __restrict__ sorted = dc->sort_final ? vals1 : vals0;
@@ -143,7 +143,9 @@ raster_backward_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ 
     const uint32_t u = L.unit;
     if (u >= n_units) break;
     const UnitInfo I = unit_info(cam, batch_tab, u);
-    stage_unit<kRasterBwdWaves>(L, I, sorted, rec, lane, wave);
+    // the tiles the forward rasterised: a tile it left out (the merge had
+    // stopped reading it) has neither a partial nor a merge state
+    stage_unit<kRasterBwdWaves>(L, I, sorted, rec, lane, wave, ~active[u]);
 
     for (;;) {
       const int t = next_tile(L, lane);
@@ -549,7 +551,7 @@ hipError_t launch_backward(int64_t n, const float* means, const float* scales, c
     hipLaunchKernelGGL(merge_backward_kernel, dim3(mblocks), dim3(kMergeBwdThreads), 0, s, cam, prm,
                        batch_first, active, partials, dc, dimg, dT, state);
   hipLaunchKernelGGL(raster_backward_kernel, dim3(n_cus * g_bwd_per_cu), dim3(kRasterBwdThreads), 0,
-                     s, cam, prm, vals2[0], vals2[1], rec, batch_tab, dc, state, dimg, dgeo);
+                     s, cam, prm, vals2[0], vals2[1], rec, batch_tab, active, dc, state, dimg, dgeo);
   if (n > 0) {
     float3 campos;
     campos.x = -(cam.R[0] * cam.t[0] + cam.R[3] * cam.t[1] + cam.R[6] * cam.t[2]);

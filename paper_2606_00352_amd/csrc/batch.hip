@@ -45,17 +45,8 @@ mt_offsets_kernel(int n_mt, const uint64_t* __restrict__ k0, const uint64_t* __r
 }
 
 constexpr int kBtThreads = 1024;
-__global__ void __launch_bounds__(kBtThreads)
-batch_table_kernel(int n_mt, uint32_t cap, uint32_t max_batches, const uint32_t* __restrict__ mt_off,
-                   DeviceCounters* __restrict__ dc, uint32_t* __restrict__ batch_first,
-                   uint32_t* __restrict__ tab) {
-  __shared__ uint32_t wave_tot[kBtThreads / 64];
-  if (dc->overflow) return;  // pairs were cut: no batch table for this frame
-  const int per = (n_mt + kBtThreads - 1) / kBtThreads;
-  const int m0 = threadIdx.x * per;
-  const int m1 = min(m0 + per, n_mt);
-  uint32_t mine = 0;
-  for (int m = m0; m < m1; ++m) mine += (mt_off[m + 1] - mt_off[m] + cap - 1) / cap;
+// Exclusive scan of one value per thread over the workgroup.
+__device__ __forceinline__ uint32_t bt_scan(uint32_t mine, uint32_t* wave_tot) {
   uint32_t v = mine;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -63,19 +54,78 @@ batch_table_kernel(int n_mt, uint32_t cap, uint32_t max_batches, const uint32_t*
     const uint32_t o = __shfl_up(v, off, 64);
     if (lane >= off) v += o;
   }
+  __syncthreads();
   if (lane == 63) wave_tot[wave] = v;
   __syncthreads();
   uint32_t run = v - mine;
   for (int w = 0; w < wave; ++w) run += wave_tot[w];
+  return run;
+}
+
+// The first batch of every macro-tile, and the raster work items: each
+// macro-tile's batches cut into runs of `chain` and a shorter remainder.  The
+// items are counted by length and listed longest first (the rasteriser claims
+// them in list order, so a long one does not end the frame alone); within a
+// length the order is that of the LDS cursor claims, which no result depends
+// on.
+__global__ void __launch_bounds__(kBtThreads)
+batch_table_kernel(int n_mt, uint32_t cap, uint32_t chain, uint32_t max_batches,
+                   const uint32_t* __restrict__ mt_off, DeviceCounters* __restrict__ dc,
+                   uint32_t* __restrict__ batch_first, uint32_t* __restrict__ chain_tab) {
+  __shared__ uint32_t wave_tot[kBtThreads / 64];
+  __shared__ uint32_t n_len[kMaxChain + 1];  // items of each length, then their next slot
+  __shared__ uint32_t total;
+  if (dc->overflow) return;  // pairs were cut: no batch table for this frame
+  if (threadIdx.x <= kMaxChain) n_len[threadIdx.x] = 0u;
+  const int per = (n_mt + kBtThreads - 1) / kBtThreads;
+  const int m0 = threadIdx.x * per;
+  const int m1 = min(m0 + per, n_mt);
+  uint32_t mine = 0;
+  for (int m = m0; m < m1; ++m) mine += (mt_off[m + 1] - mt_off[m] + cap - 1) / cap;
+  const uint32_t run0 = bt_scan(mine, wave_tot);  // (its first barrier orders n_len's clearing)
+  uint32_t run = run0;
   for (int m = m0; m < m1; ++m) {
+    const uint32_t nb = (mt_off[m + 1] - mt_off[m] + cap - 1) / cap;
     batch_first[m] = run;
-    run += (mt_off[m + 1] - mt_off[m] + cap - 1) / cap;
+    run += nb;
+    if (nb >= chain) atomicAdd(&n_len[chain], nb / chain);
+    if (nb % chain) atomicAdd(&n_len[nb % chain], 1u);
   }
+  __syncthreads();
   if (threadIdx.x == kBtThreads - 1) {
+    uint32_t at = 0;
+    for (int l = (int)chain; l >= 1; --l) {
+      const uint32_t c = n_len[l];
+      n_len[l] = at;
+      at += c;
+    }
+    total = run;
     batch_first[n_mt] = run;
     dc->n_batches_total = run;
     dc->n_batches = run < max_batches ? run : max_batches;
+    dc->n_chains = run > max_batches ? 0u : at;
     if (run > max_batches) dc->overflow |= HIGS_OVF_BATCHES;
+  }
+  __syncthreads();
+  if (total > max_batches) return;  // (uniform) the frame stops; no work items
+  // the rows (first batch, batches): every item fits, as items <= batches
+  uint32_t first = run0;
+  for (int m = m0; m < m1; ++m) {
+    const uint32_t nb = (mt_off[m + 1] - mt_off[m] + cap - 1) / cap;
+    const uint32_t n_full = nb / chain, rest = nb - n_full * chain;
+    if (n_full) {
+      const uint32_t at = atomicAdd(&n_len[chain], n_full);
+      for (uint32_t c = 0; c < n_full; ++c) {
+        chain_tab[2 * (at + c) + 0] = first + c * chain;
+        chain_tab[2 * (at + c) + 1] = chain;
+      }
+    }
+    if (rest) {
+      const uint32_t at = atomicAdd(&n_len[rest], 1u);
+      chain_tab[2 * at + 0] = first + n_full * chain;
+      chain_tab[2 * at + 1] = rest;
+    }
+    first += nb;
   }
 }
 
@@ -102,12 +152,13 @@ batch_rows_kernel(int n_mt, uint32_t cap, uint32_t max_batches,
   }
 }
 
-// batch_first by one workgroup, then the rows by a wave per macro-tile
+// batch_first and the work items by one workgroup, then the batch rows by a
+// wave per macro-tile
 static void launch_table(int n_mt, uint32_t batch_cap, uint32_t max_batches, DeviceCounters* dc,
                          const uint32_t* mt_off, uint32_t* batch_first, uint32_t* batch_tab,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(batch_table_kernel, dim3(1), dim3(kBtThreads), 0, s, n_mt, batch_cap,
-                     max_batches, mt_off, dc, batch_first, batch_tab);
+                         ChainBuffers cb, hipStream_t s) {
+  hipLaunchKernelGGL(batch_table_kernel, dim3(1), dim3(kBtThreads), 0, s, n_mt, batch_cap, cb.chain,
+                     max_batches, mt_off, dc, batch_first, cb.tab);
   const int row_blocks = (n_mt + (kOffThreads / 64) - 1) / (kOffThreads / 64);
   if (row_blocks > 0)
     hipLaunchKernelGGL(batch_rows_kernel, dim3(row_blocks), dim3(kOffThreads), 0, s, n_mt,
@@ -116,19 +167,20 @@ static void launch_table(int n_mt, uint32_t batch_cap, uint32_t max_batches, Dev
 
 hipError_t launch_batch(int n_mt, uint32_t batch_cap, uint32_t max_batches, const uint64_t* const* keys2,
                         DeviceCounters* dc, uint32_t* mt_off, uint32_t* batch_first,
-                        uint32_t* batch_tab, hipStream_t s) {
+                        uint32_t* batch_tab, ChainBuffers cb, hipStream_t s) {
   const int waves = n_mt + 1;
   const int blocks = (waves + (kOffThreads / 64) - 1) / (kOffThreads / 64);
   hipLaunchKernelGGL(mt_offsets_kernel, dim3(blocks), dim3(kOffThreads), 0, s, n_mt, keys2[0],
                      keys2[1], dc, mt_off);
-  launch_table(n_mt, batch_cap, max_batches, dc, mt_off, batch_first, batch_tab, s);
+  launch_table(n_mt, batch_cap, max_batches, dc, mt_off, batch_first, batch_tab, cb, s);
   return hipGetLastError();
 }
 
 hipError_t launch_batch_from_offsets(int n_mt, uint32_t batch_cap, uint32_t max_batches,
                                      DeviceCounters* dc, const uint32_t* mt_off,
-                                     uint32_t* batch_first, uint32_t* batch_tab, hipStream_t s) {
-  launch_table(n_mt, batch_cap, max_batches, dc, mt_off, batch_first, batch_tab, s);
+                                     uint32_t* batch_first, uint32_t* batch_tab, ChainBuffers cb,
+                                     hipStream_t s) {
+  launch_table(n_mt, batch_cap, max_batches, dc, mt_off, batch_first, batch_tab, cb, s);
   return hipGetLastError();
 }
 

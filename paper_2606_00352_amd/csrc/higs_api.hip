@@ -42,6 +42,8 @@ struct higs_ctx {
   uint64_t* status = nullptr;
   uint32_t max_tiles = 0;
   uint32_t *mt_off = nullptr, *batch_first = nullptr, *batch_tab = nullptr, *active = nullptr;
+  uint32_t* chain_tab = nullptr;  // raster work items (runs of batches of a macro-tile)
+  float* chain_T = nullptr;  // [kMaxRasterWorkers][32 tiles][64 px] transmittance products
   float4* partials = nullptr;
   DeviceCounters* dc = nullptr;
   // segmented sort: per macro-tile counts, fill cursors, chunk and block tables
@@ -169,7 +171,8 @@ void free_all(higs_ctx* c) {
     void* bufs[] = {c->f_mx, c->f_my, c->f_a, c->f_b, c->f_c, c->f_tau, c->f_key, c->f_cnt,
                     c->f_span, c->rec, c->block_sums, c->keys[0], c->keys[1], c->vals[0],
                     c->vals[1], c->hist, c->plan, c->status, c->mt_off, c->batch_first,
-                    c->batch_tab, c->active, c->partials, c->dc, c->seg_cm, c->seg_off,
+                    c->batch_tab, c->active, c->partials, c->dc, c->chain_tab,
+                    c->chain_T, c->seg_cm, c->seg_off,
                     c->seg_tiles, c->seg_list, c->view_table};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
@@ -222,6 +225,8 @@ void for_each_buffer(higs_ctx* c, F&& f) {
   f(&c->mt_off, mt + 1);
   f(&c->batch_first, mt + 1);
   f(&c->batch_tab, 3 * B);
+  f(&c->chain_tab, 2 * B);
+  f(&c->chain_T, (size_t)kMaxRasterWorkers * kTilesPerMt * 64);
   f(&c->active, B);
   f(&c->partials, B * kTilesPerMt * 64);
   f(&c->dc, (size_t)1);
@@ -316,6 +321,7 @@ void higs_default_params(higs_params* p) {
   p->sh_format = HIGS_SH_FLOAT32;
   p->max_views = 1;
   p->use_graphs = 0;
+  p->raster_chain = 64;
 }
 
 const char* higs_error_string(int code) {
@@ -361,6 +367,7 @@ int check_params(const higs_params& p, int64_t max_gaussians, int64_t max_pairs,
   // virtual gaussian ids (the view's range, then the gaussian) are 32-bit
   if ((int64_t)p.max_views * pad_blocks(max_gaussians) > (int64_t)0xffffffff) return HIGS_E_INVALID;
   if (p.use_graphs != 0 && p.use_graphs != 1) return HIGS_E_INVALID;
+  if (p.raster_chain < 1 || p.raster_chain > kMaxChain) return HIGS_E_INVALID;
   return HIGS_OK;
 }
 
@@ -647,6 +654,7 @@ int project_frame(higs_ctx* c, const higs_camera* cam0, hipStream_t s, bool capt
   c->pa.dilation = c->params.dilation;
   c->pa.batch_cap = c->params.batch_cap;
   c->pa.sh_degree = c->params.sh_degree;
+  c->pa.chain = c->params.raster_chain;
   c->n_mt = a.n_mt_x * a.n_mt_y;
   c->n_mt_all = c->n_mt * c->n_views;
   c->views.n_mt = c->n_mt;
@@ -809,16 +817,20 @@ int higs_batch(higs_ctx* c, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
   const uint64_t* k2[2] = {c->keys[0], c->keys[1]};
+  // chains apply to the float32 rasteriser; the other keeps one batch per item
+  ChainBuffers cb;
+  cb.chain = c->params.raster_precision == HIGS_RASTER_FP32 ? (uint32_t)c->params.raster_chain : 1u;
+  cb.tab = c->chain_tab;
   int rc;
   {
     TimerScope ts(c, HIGS_TIMER_BATCH, s);
     if (c->segmented())
       rc = hip_err(launch_batch_from_offsets(c->n_mt, (uint32_t)c->params.batch_cap,
                                              (uint32_t)c->max_batches, c->dc, c->mt_off,
-                                             c->batch_first, c->batch_tab, s));
+                                             c->batch_first, c->batch_tab, cb, s));
     else
       rc = hip_err(launch_batch(c->n_mt_all, (uint32_t)c->params.batch_cap, (uint32_t)c->max_batches,
-                                k2, c->dc, c->mt_off, c->batch_first, c->batch_tab, s));
+                                k2, c->dc, c->mt_off, c->batch_first, c->batch_tab, cb, s));
   }
   if (rc) return rc;
   c->stage = 3;
@@ -841,8 +853,8 @@ int raster_frame(higs_ctx* c, hipStream_t s) {
       rc = hip_err(launch_raster16(c->ca, c->pa, v2, c->rec, c->batch_tab, c->dc, c->partials,
                                    c->active, c->n_cus, count, s));
     else
-      rc = hip_err(launch_raster(c->ca, c->pa, v2, c->rec, c->batch_tab, c->dc, c->partials,
-                                 c->active, c->n_cus, count, s));
+      rc = hip_err(launch_raster(c->ca, c->pa, v2, c->rec, c->batch_tab, c->chain_tab, c->dc,
+                                 c->partials, c->active, c->chain_T, c->n_cus, count, s));
   }
   if (rc) return rc;
   {

@@ -18,6 +18,7 @@ constexpr int kMtW = kTile * kMtTilesX;  // 64
 constexpr int kMtH = kTile * kMtTilesY;  // 32
 constexpr int kTilesPerMt = kMtTilesX * kMtTilesY;  // 32
 constexpr int kMaxBatch = 1024;  // largest B_r the rasteriser's LDS holds
+constexpr int kMaxChain = 64;    // most batches of one raster work item
 
 constexpr int kProjBlock = 256;  // gaussians per projection / emission block
 constexpr int kFillGroup = 4;    // projection blocks per emission workgroup
@@ -87,6 +88,7 @@ struct DeviceCounters {
                                                  //   one per merge level
   uint32_t seg_tier_n[kSegTiers];  // segments in each tier (tier 3: long segments)
   uint32_t seg_chunks;      // chunks of the long segments
+  uint32_t n_chains;        // raster work items: runs of up to `chain` batches of a macro-tile
   uint32_t id_shift;        // > 0: each pair is one word key << id_shift | id (see scan_kernel)
   uint32_t sort_last;       // last radix pass that moves data (it writes the id array)
   uint32_t pad[6];
@@ -121,7 +123,11 @@ struct CamArgs {
 struct ParamArgs {
   float alpha_max, t_eps, near_z, dilation;
   int32_t batch_cap, sh_degree;
+  int32_t chain;  // batches of a macro-tile per raster work item
 };
+
+// Raster workgroups the chain scratch is sized for (grid bound).
+constexpr int kMaxRasterWorkers = 1024;
 
 // A frame of several views (cameras of one image size, each with its own
 // scene arrays and image): view v owns the virtual gaussians
@@ -188,14 +194,22 @@ struct SortBuffers {
 hipError_t launch_sort(int n_passes, int mt_bits, SortBuffers sb,
                        DeviceCounters* dc, int n_cus, hipStream_t s);
 
+// Raster work items: runs of up to `chain` consecutive batches of one
+// macro-tile; tab rows are (first batch, batches), longest runs first.
+struct ChainBuffers {
+  uint32_t chain;
+  uint32_t* tab;    // [max_batches][2]
+};
+
 hipError_t launch_batch(int n_mt, uint32_t batch_cap, uint32_t max_batches, const uint64_t* const* keys2,
                         DeviceCounters* dc, uint32_t* mt_off, uint32_t* batch_first,
-                        uint32_t* batch_tab, hipStream_t s);
+                        uint32_t* batch_tab, ChainBuffers cb, hipStream_t s);
 
 hipError_t launch_raster(CamArgs cam, ParamArgs prm, const uint32_t* const* vals2,
                          const RasterRecord* rec, const uint32_t* batch_tab,
-                         DeviceCounters* dc, float4* partials, uint32_t* active, int n_cus,
-                         bool count_evals, hipStream_t s);
+                         const uint32_t* chain_tab, DeviceCounters* dc, float4* partials,
+                         uint32_t* active, float* chain_T, int n_cus, bool count_evals,
+                         hipStream_t s);
 
 // Half-precision rasteriser and merge; the partials buffer then holds four
 // halves per pixel.
@@ -249,7 +263,8 @@ hipError_t launch_seg_sort(int64_t n, int n_mt, SegBuffers sb, uint32_t max_pair
 // Batch table from segment offsets already computed (segmented sort).
 hipError_t launch_batch_from_offsets(int n_mt, uint32_t batch_cap, uint32_t max_batches,
                                      DeviceCounters* dc, const uint32_t* mt_off,
-                                     uint32_t* batch_first, uint32_t* batch_tab, hipStream_t s);
+                                     uint32_t* batch_first, uint32_t* batch_tab, ChainBuffers cb,
+                                     hipStream_t s);
 
 int raster_workers_per_cu();
 // Resident workgroups per CU of the persistent kernels, queried once per

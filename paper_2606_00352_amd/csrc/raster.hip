@@ -33,66 +33,102 @@ template <bool kCountEvals>
 __global__ void __launch_bounds__(kRasterThreads)
 raster_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ vals0,
               const uint32_t* __restrict__ vals1, const RasterRecord* __restrict__ rec,
-              const uint32_t* __restrict__ batch_tab, DeviceCounters* __restrict__ dc,
-              float4* __restrict__ partials, uint32_t* __restrict__ active) {
+              const uint32_t* __restrict__ batch_tab, const uint32_t* __restrict__ chain_tab,
+              DeviceCounters* __restrict__ dc, float4* __restrict__ partials,
+              uint32_t* __restrict__ active, float* __restrict__ chain_T) {
   __shared__ RasterLds L;
   if (dc->overflow) return;  // the frame stops at a capacity overflow
   const uint32_t* __restrict__ sorted = dc->sort_final ? vals1 : vals0;
-  const uint32_t n_units = dc->n_batches;
+  const uint32_t n_chains = dc->n_chains;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const float eps = prm.t_eps, amax = prm.alpha_max;
   const float pxo = (float)(lane & 7) + 0.5f, pyo = (float)(lane >> 3) + 0.5f;
+  // this workgroup's products of the batch transmittances along a chain
+  float* __restrict__ myT = chain_T + (size_t)blockIdx.x * kTilesPerMt * 64;
 
+  uint64_t evals_all = 0;  // this wave's evaluations (the count-evals variant)
   for (;;) {
-    if (tid == 0) {
-      L.unit = atomicAdd(&dc->raster_next, 1u);
-      L.qnext = 0;
-    }
+    if (tid == 0) L.unit = atomicAdd(&dc->raster_next, 1u);
+    if (tid < kTilesPerMt) L.tstate[tid] = 0u;
     __syncthreads();
-    const uint32_t u = L.unit;
-    if (u >= n_units) break;
-    const UnitInfo I = unit_info(cam, batch_tab, u);
-    const uint32_t act = stage_unit<kRasterWaves>(L, I, sorted, rec, lane, wave);
-    if (tid == 0) active[u] = act;
-
-    // Phase 2: waves claim tiles
-    for (;;) {
-      const int t = next_tile(L, lane);
-      if (t < 0) break;
-      const float pxr = (float)((t & 7) * kTile) + pxo;
-      const float pyr = (float)((t >> 3) * kTile) + pyo;
-      float cr = 0.0f, cg = 0.0f, cb = 0.0f, T = 1.0f;
-      uint32_t evals = 0;
-      for (int k = 0; k < I.K; ++k) {
-        uint64_t m = uniform64(L.masks[k][t]);
-        if (kCountEvals) evals += (uint32_t)__popcll(m);
-        while (m) {
-          const int j = __ffsll((unsigned long long)m) - 1;
-          m &= m - 1ull;
-          const int gi = k * 64 + j;
-          const float4 A = L.ga[gi];
-          const float4 B = L.gb[gi];  // l2', log2 o, r, g
-          const float bb = L.gc[gi].x;
-          const float al = eval_alpha(A, B, B.y, pxr, pyr, amax).al;
-          // branchless blend: a skipped gaussian adds w = 0 and keeps T
-          // exactly; T(1 - a) is one fused T - aT, rounded once (the
-          // adjoint's replay forms it the same way)
-          const float a = (T >= eps && al >= kAlphaMin) ? al : 0.0f;
-          const float w = a * T;
-          cr += w * B.z;
-          cg += w * B.w;
-          cb += w * bb;
-          T = fmaf(-a, T, T);
-        }
-        if (__ballot(T >= eps) == 0) break;
+    const uint32_t ch = L.unit;
+    if (ch >= n_chains) break;
+    const uint32_t u0 = chain_tab[2 * ch], n_u = chain_tab[2 * ch + 1];
+    for (uint32_t i = 0; i < n_u; ++i) {
+      const uint32_t u = u0 + i;
+      const UnitInfo I = unit_info(cam, batch_tab, u);
+      // the render tiles inside the image, and those the chain's earlier
+      // batches saturated (read after the barrier that ended the last unit)
+      uint32_t inside = 0;
+      for (int r = 0; r < I.tiles_y; ++r) inside |= (0xffu >> (kMtTilesX - I.tiles_x)) << (r * kMtTilesX);
+      const uint32_t sat = (uint32_t)__ballot(lane < kTilesPerMt && L.tstate[lane & (kTilesPerMt - 1)] == 2u);
+      if ((sat & inside) == inside) {  // the merge reads nothing of this unit
+        if (tid == 0) active[u] = 0u;
+        continue;
       }
-      if (kCountEvals && lane == 0) atomicAdd(&dc->n_evals, (unsigned long long)evals);
-      v4f* dst = reinterpret_cast<v4f*>(partials + (((size_t)u * kTilesPerMt + t) * 64 + lane));
-      const v4f val = {cr, cg, cb, T};
-      __builtin_nontemporal_store(val, dst);
+      if (tid == 0) L.qnext = 0;
+      const uint32_t act = stage_unit<kRasterWaves>(L, I, sorted, rec, lane, wave, sat);
+      if (tid == 0) active[u] = act;
+
+      // Phase 2: waves claim tiles
+      for (;;) {
+        const int t = next_tile(L, lane);
+        if (t < 0) break;
+        const float pxr = (float)((t & 7) * kTile) + pxo;
+        const float pyr = (float)((t >> 3) * kTile) + pyo;
+        float cr = 0.0f, cg = 0.0f, cb = 0.0f, T = 1.0f;
+        uint32_t evals = 0;
+        for (int k = 0; k < I.K; ++k) {
+          uint64_t m = uniform64(L.masks[k][t]);
+          if (kCountEvals) evals += (uint32_t)__popcll(m);
+          while (m) {
+            const int j = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1ull;
+            const int gi = k * 64 + j;
+            const float4 A = L.ga[gi];
+            const float4 B = L.gb[gi];  // l2', log2 o, r, g
+            const float bb = L.gc[gi].x;
+            const float al = eval_alpha(A, B, B.y, pxr, pyr, amax).al;
+            // branchless blend: a skipped gaussian adds w = 0 and keeps T
+            // exactly; T(1 - a) is one fused T - aT, rounded once (the
+            // adjoint's replay forms it the same way)
+            const float a = (T >= eps && al >= kAlphaMin) ? al : 0.0f;
+            const float w = a * T;
+            cr += w * B.z;
+            cg += w * B.w;
+            cb += w * bb;
+            T = fmaf(-a, T, T);
+          }
+          if (__ballot(T >= eps) == 0) break;
+        }
+        if (kCountEvals) evals_all += evals;
+        v4f* dst = reinterpret_cast<v4f*>(partials + (((size_t)u * kTilesPerMt + t) * 64 + lane));
+        const v4f val = {cr, cg, cb, T};
+        __builtin_nontemporal_store(val, dst);
+        if (i + 1 < n_u) {
+          // the tile's product of T over the chain so far, in the order and
+          // the float32 arithmetic of the merge: with t_eps reached at every
+          // pixel, the merge (whose own product is never larger) has stopped
+          // reading this tile, and the chain's later batches leave it out.
+          // Only this wave writes the tile's state in this unit, and every
+          // lane stores the same word: no lane-0 branch in this loop, which
+          // would let the compiler split the wave around next_tile's
+          // readfirstlane
+          float* __restrict__ pt = myT + t * 64 + lane;
+          const uint32_t st = L.tstate[t];
+          const float prod = st == 0u ? T : *pt * T;
+          *pt = prod;
+          const bool done = __ballot(prod >= eps) == 0ull;
+          L.tstate[t] = done ? 2u : 1u;
+        }
+      }
+      __syncthreads();
     }
+    // a chain that ended on a left-out unit has not passed the barrier above:
+    // no wave may still read the tile states when the next chain resets them
     __syncthreads();
   }
+  if (kCountEvals && lane == 0) atomicAdd(&dc->n_evals, (unsigned long long)evals_all);
 }
 
 constexpr int kMergeThreads = 256;
@@ -183,15 +219,18 @@ int raster_per_cu_config() {
 
 hipError_t launch_raster(CamArgs cam, ParamArgs prm, const uint32_t* const* vals2,
                          const RasterRecord* rec, const uint32_t* batch_tab,
-                         DeviceCounters* dc, float4* partials, uint32_t* active, int n_cus,
-                         bool count_evals, hipStream_t s) {
+                         const uint32_t* chain_tab, DeviceCounters* dc, float4* partials,
+                         uint32_t* active, float* chain_T, int n_cus, bool count_evals,
+                         hipStream_t s) {
   raster_per_cu_config();
+  // one chain scratch slice per workgroup of the grid
+  const int grid = min(n_cus * g_raster_per_cu, kMaxRasterWorkers);
   if (count_evals)
-    hipLaunchKernelGGL(raster_kernel<true>, dim3(n_cus * g_raster_per_cu), dim3(kRasterThreads), 0, s,
-                       cam, prm, vals2[0], vals2[1], rec, batch_tab, dc, partials, active);
+    hipLaunchKernelGGL(raster_kernel<true>, dim3(grid), dim3(kRasterThreads), 0, s, cam, prm,
+                       vals2[0], vals2[1], rec, batch_tab, chain_tab, dc, partials, active, chain_T);
   else
-    hipLaunchKernelGGL(raster_kernel<false>, dim3(n_cus * g_raster_per_cu), dim3(kRasterThreads), 0,
-                       s, cam, prm, vals2[0], vals2[1], rec, batch_tab, dc, partials, active);
+    hipLaunchKernelGGL(raster_kernel<false>, dim3(grid), dim3(kRasterThreads), 0, s, cam, prm,
+                       vals2[0], vals2[1], rec, batch_tab, chain_tab, dc, partials, active, chain_T);
   return hipGetLastError();
 }
 

@@ -22,6 +22,9 @@ struct RasterLds {
   uint32_t qcount;
   uint32_t qnext;
   uint32_t unit;
+  // per render tile along a chain of batches: 0 = no product stored yet,
+  // 1 = product of T stored, 2 = product below t_eps at every pixel
+  uint32_t tstate[kTilesPerMt];
 };
 
 // Conservative test of one gaussian against the macro-tile's render tiles:
@@ -115,13 +118,14 @@ __device__ __forceinline__ UnitInfo unit_info(const CamArgs& cam, const uint32_t
 // records by sorted id into LDS (macro-tile-relative, factors prescaled),
 // tests each gaussian against the render tiles and transposes the 32-bit
 // per-gaussian tile masks into 64-bit per-tile gaussian masks (a butterfly
-// bit-matrix transpose).  Then wave 0 builds the queue of tiles with any gaussian and
-// returns their mask (in lane 0 of wave 0).  Ends with a barrier.
+// bit-matrix transpose).  Then wave 0 builds the queue of tiles with any
+// gaussian, leaving out the tiles of `skip`, and returns their mask (in lane 0
+// of wave 0).  Ends with a barrier.
 template <int kWavesPerGroup>
 __device__ __forceinline__ uint32_t stage_unit(RasterLds& L, const UnitInfo& I,
                                                const uint32_t* __restrict__ sorted,
                                                const RasterRecord* __restrict__ rec, int lane,
-                                               int wave) {
+                                               int wave, uint32_t skip = 0u) {
   for (int k = wave; k < I.K; k += kWavesPerGroup) {
     const int j = k * 64 + lane;
     uint32_t tmask = 0;
@@ -164,9 +168,9 @@ __device__ __forceinline__ uint32_t stage_unit(RasterLds& L, const UnitInfo& I,
     uint64_t hit = 0;
     if (lane < kTilesPerMt)
       for (int k = 0; k < I.K; ++k) hit |= L.masks[k][lane];
-    const uint64_t act = __ballot(lane < kTilesPerMt && hit != 0);
-    if (lane < kTilesPerMt && hit != 0)
-      L.queue[__popcll(act & ((1ull << lane) - 1ull))] = (uint32_t)lane;
+    const bool take = lane < kTilesPerMt && hit != 0 && !((skip >> lane) & 1u);
+    const uint64_t act = __ballot(take);
+    if (take) L.queue[__popcll(act & ((1ull << lane) - 1ull))] = (uint32_t)lane;
     if (lane == 0) L.qcount = (uint32_t)__popcll(act);
     act32 = (uint32_t)act;
   }

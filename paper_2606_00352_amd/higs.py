@@ -47,7 +47,8 @@ class Params(ctypes.Structure):
                 ("t_eps", ctypes.c_float), ("near_z", ctypes.c_float),
                 ("dilation", ctypes.c_float), ("sort_mode", ctypes.c_int32),
                 ("raster_precision", ctypes.c_int32), ("sh_format", ctypes.c_int32),
-                ("max_views", ctypes.c_int32), ("use_graphs", ctypes.c_int32)]
+                ("max_views", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
+                ("raster_chain", ctypes.c_int32)]
 
 
 class CameraC(ctypes.Structure):

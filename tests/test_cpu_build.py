@@ -196,3 +196,36 @@ def test_segmented_sort_matches_the_oracle(orc, case):
     assert np.array_equal(fr.batches.astype(np.int64), o.batch_tab.astype(np.int64))
     if case == "long_segment":
         assert fr.n_pairs > 32768
+
+
+def test_raster_chains_skip_saturated_tiles(orc):
+    """A raster work item of several batches of one macro-tile leaves out the
+    render tiles whose product of transmittances over its earlier batches is
+    below t_eps everywhere: the image and T are those of one batch per work
+    item, bit for bit, and of the oracle, with fewer evaluations."""
+    from paper_2606_00352_amd import higs
+    cpu = _cpu()
+    sc, cam = _dense_scene(9000, 256, 128, 256.0, 21, 20, 10, 0.004)
+    sc.opacities[:] = 0.9
+    old = os.environ.get("HIGS_CPU_DEBUG")
+    os.environ["HIGS_CPU_DEBUG"] = str(higs.DEBUG_COUNT_EVALS)
+    try:
+        one = cpu.run_frames(sc, [cam], max_pairs=1 << 16, max_batches=256, batch_cap=256, chain=1)[0]
+        # runs of three (items of lengths 3, 2 and 1 in one list) and whole macro-tiles
+        three = cpu.run_frames(sc, [cam], max_pairs=1 << 16, max_batches=256, batch_cap=256, chain=3)[0]
+        many = cpu.run_frames(sc, [cam], max_pairs=1 << 16, max_batches=256, batch_cap=256, chain=64)[0]
+    finally:
+        if old is None:
+            del os.environ["HIGS_CPU_DEBUG"]
+        else:
+            os.environ["HIGS_CPU_DEBUG"] = old
+    assert one.rc == 0 and three.rc == 0 and many.rc == 0 and one.n_batches > 8
+    for r in (three, many):
+        assert np.array_equal(one.image, r.image) and np.array_equal(one.T, r.T)
+    assert 0 < many.n_evaluations <= three.n_evaluations <= one.n_evaluations
+    assert many.n_evaluations < one.n_evaluations
+    prm = orc.Params()
+    prm.batch_cap = 256
+    o = orc.frame(sc, cam, prm)
+    d = np.abs(many.image.astype(np.float64) - o.image)
+    assert d[o.amb == 0].max() <= 2e-4 and d.mean() <= 1e-5

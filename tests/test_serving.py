@@ -25,11 +25,12 @@ def test_context_footprint_counts_every_array():
     nchunk = (nblk + 255) // 256          # scan chunks of 256 projection blocks
     want = (G * (9 * 4 + 48) + 2 * nblk * 4 + 2 * nchunk * 4 + P * 24 + 8 * radix * 4 + (8 + 8 * radix) * 4
             + tiles * radix * 8
-            + 2 * (n_mt + 1) * 4 + B * 16 + B * 32 * 64 * 16)
+            + 2 * (n_mt + 1) * 4 + B * 16 + B * 32 * 64 * 16 + B * 8   # + raster work items
+            + 1024 * 32 * 64 * 4)                                        # chain products, 1,024 workers
     got = higs.ctx_footprint(G, P, B, W, H)
     assert 0 < got - want <= 1024         # plus the frame counters and the view table
     assert higs.ctx_footprint(G, 2 * P, B, W, H) > got
-    assert higs.ctx_footprint(G, P, 2 * B, W, H) - got == B * (16 + 32 * 64 * 16)
+    assert higs.ctx_footprint(G, P, 2 * B, W, H) - got == B * (16 + 32 * 64 * 16 + 8)
     assert higs.ctx_footprint(0, P, B, W, H) == higs.E_INVALID
     # four views per frame: four ranges of gaussians and of macro-tiles
     four = higs.ctx_footprint(G, P, B, W, H, max_views=4)
