@@ -58,14 +58,14 @@ COPY_CALIBRATION_BYTES = 1 << 30
 MEASURED_TRAFFIC = {
     # profiles/frame_1080p_5p8m_hbm_traffic.md (sort: histogram + plan + every
     # onesweep dispatch of a frame)
-    "raster": {"src_sha256": "b3e2e7325d9e435d42dba4fa71f099aeb5983ec5b986eccbe644fd24f63ecfb5",
-              "bytes_per_launch": 656400000},
-    "project": {"src_sha256": "0925caeb56485ff4867530c328f7dec71cbfe6860d4efb751909bc554f8573b2",
+    "raster": {"src_sha256": "d5edc9598e8ab03901064fae92010907ad0046e17fb7f4c48b2af5e544be5ca6",
+              "bytes_per_launch": 730400000},
+    "project": {"src_sha256": "114e4896592950c5b77f6cf5ad370dcdcb84d2e6bbb144933097b012bc3d6273",
                "bytes_per_launch": 1714600000},
-    "fill": {"src_sha256": "96a574c29be0bd13eed704f4a86e70d83788d3fa8fc3465abfe0d2a8c39ec06a",
+    "fill": {"src_sha256": "7cee7960649929cb46d4a693074549546c05d393ddc0924fd483f4806551217e",
             "bytes_per_launch": 134900000},
-    "sort": {"src_sha256": "d8269cab929ef5c659af18391e4db2805e599524012bfdcc484e70451c473eba",
-            "bytes_per_launch": 920800000},
+    "sort": {"src_sha256": "c71ad7dc51ac2e8b1de9929e10927334857ff8aa5bbdfc82126ee6063bfc77a8",
+            "bytes_per_launch": 923900000},
 }
 # the sources each figure depends on (the shared header holds the kernels' shapes)
 KERNEL_SOURCES = {"project": ("project.hip", "predicate.h", "higs_internal.h"),
@@ -164,14 +164,16 @@ def scenes_config0():
 def backward_leg(n=1_000_000, warmup=5, steps=20):
     """Differentiable render at its workload size (1M clustered gaussians,
     1920x1080, view 0 of the orbit): mean ms of forward-only frames and of
-    forward + adjoint (higs_raster_backward) frames, HIP-synchronised."""
+    forward + adjoint (higs_raster_backward) frames, HIP-synchronised.  The
+    context keeps the partials and runs the merge kernel (fuse_merge = 0, the
+    setting for training: the adjoint reads the partials)."""
     import numpy as np
     import torch
     from paper_2606_00352_amd import higs, scenes
     scene = scenes.clustered_scene(n, seed=4)
     cam = scenes.orbit_cameras(60, 101, 1920, 1080, 1100.0)[0]
     tens = higs.scene_tensors(scene, "cuda:0")
-    ctx = higs.Context(scene.n, 1920, 1080)
+    ctx = higs.Context(scene.n, 1920, 1080, fuse_merge=0)
     image = torch.empty((1080, 1920, 3), dtype=torch.float32, device="cuda:0")
     T = torch.empty((1080, 1920), dtype=torch.float32, device="cuda:0")
     rng = np.random.default_rng(40)

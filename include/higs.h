@@ -98,6 +98,13 @@ typedef struct {
                            of the earlier batches' transmittances is below t_eps at all 64 of
                            its pixels, where the merge of Eq. 1 stops reading; 1: every
                            (macro-tile, batch) unit is rasterised in full */
+  int32_t fuse_merge;   /* 1 (default): a float32 raster work item takes all batches of one
+                           macro-tile and folds their partials into its pixels itself, by
+                           Eq. 1 in the merge's order and arithmetic (the same image and T,
+                           bit for bit); no partials are stored, no merge kernel runs, and
+                           raster_chain is not used.  0: the partials and the merge kernel,
+                           which higs_raster_backward reads (with 1 it first rasterises the
+                           frame again with partials) */
 } higs_params;
 
 #define HIGS_MAX_VIEWS 64
@@ -431,7 +438,9 @@ int higs_get_counts(higs_ctx* ctx, higs_counts* out);
 #define HIGS_DBG_SORTED 4   /* same layout, sorted */
 #define HIGS_DBG_MT_OFFSETS 5 /* uint32 [n_macro_tiles + 1]: first sorted pair of each macro-tile */
 #define HIGS_DBG_BATCHES 6  /* uint32 [n_batches][3]: macro-tile, start, length */
-#define HIGS_DBG_ACTIVE 7   /* uint32 [n_batches]: bit t = render tile t written by the unit */
+#define HIGS_DBG_ACTIVE 7   /* uint32 [n_batches]: bit t = render tile t written by the unit
+                               (ACTIVE and PARTIALS: frames with fuse_merge = 0, else
+                               HIGS_E_STATE) */
 #define HIGS_DBG_PARTIALS 8 /* float32 [n_batches][32][64][4]: R, G, B, T per pixel, valid
                                where the active bit is set; pixel p of tile t sits at
                                (t % 8 * 8 + p % 8, t / 8 * 8 + p / 8) in the macro-tile */

@@ -63,13 +63,14 @@ __device__ __forceinline__ uint32_t bt_scan(uint32_t mine, uint32_t* wave_tot) {
 }
 
 // The first batch of every macro-tile, and the raster work items: each
-// macro-tile's batches cut into runs of `chain` and a shorter remainder.  The
-// items are counted by length and listed longest first (the rasteriser claims
-// them in list order, so a long one does not end the frame alone); within a
-// length the order is that of the LDS cursor claims, which no result depends
-// on.
+// macro-tile's batches cut into runs of `chain` and a shorter remainder, or
+// (whole) every macro-tile with all its batches, empty ones included.  The
+// items are counted by length (lengths above kMaxChain count as kMaxChain) and
+// listed longest first (the rasteriser claims them in list order, so a long
+// one does not end the frame alone); within a length the order is that of the
+// LDS cursor claims, which no result depends on.
 __global__ void __launch_bounds__(kBtThreads)
-batch_table_kernel(int n_mt, uint32_t cap, uint32_t chain, uint32_t max_batches,
+batch_table_kernel(int n_mt, uint32_t cap, uint32_t chain, bool whole, uint32_t max_batches,
                    const uint32_t* __restrict__ mt_off, DeviceCounters* __restrict__ dc,
                    uint32_t* __restrict__ batch_first, uint32_t* __restrict__ chain_tab) {
   __shared__ uint32_t wave_tot[kBtThreads / 64];
@@ -88,13 +89,17 @@ batch_table_kernel(int n_mt, uint32_t cap, uint32_t chain, uint32_t max_batches,
     const uint32_t nb = (mt_off[m + 1] - mt_off[m] + cap - 1) / cap;
     batch_first[m] = run;
     run += nb;
-    if (nb >= chain) atomicAdd(&n_len[chain], nb / chain);
-    if (nb % chain) atomicAdd(&n_len[nb % chain], 1u);
+    if (whole) {
+      atomicAdd(&n_len[min(nb, (uint32_t)kMaxChain)], 1u);
+    } else {
+      if (nb >= chain) atomicAdd(&n_len[chain], nb / chain);
+      if (nb % chain) atomicAdd(&n_len[nb % chain], 1u);
+    }
   }
   __syncthreads();
   if (threadIdx.x == kBtThreads - 1) {
     uint32_t at = 0;
-    for (int l = (int)chain; l >= 1; --l) {
+    for (int l = whole ? kMaxChain : (int)chain; l >= (whole ? 0 : 1); --l) {
       const uint32_t c = n_len[l];
       n_len[l] = at;
       at += c;
@@ -108,22 +113,31 @@ batch_table_kernel(int n_mt, uint32_t cap, uint32_t chain, uint32_t max_batches,
   }
   __syncthreads();
   if (total > max_batches) return;  // (uniform) the frame stops; no work items
-  // the rows (first batch, batches): every item fits, as items <= batches
+  // the rows: items <= batches (+ macro-tiles when whole), the table's rows
   uint32_t first = run0;
   for (int m = m0; m < m1; ++m) {
     const uint32_t nb = (mt_off[m + 1] - mt_off[m] + cap - 1) / cap;
-    const uint32_t n_full = nb / chain, rest = nb - n_full * chain;
-    if (n_full) {
-      const uint32_t at = atomicAdd(&n_len[chain], n_full);
-      for (uint32_t c = 0; c < n_full; ++c) {
-        chain_tab[2 * (at + c) + 0] = first + c * chain;
-        chain_tab[2 * (at + c) + 1] = chain;
+    if (whole) {
+      const uint32_t at = atomicAdd(&n_len[min(nb, (uint32_t)kMaxChain)], 1u);
+      chain_tab[3 * at + 0] = (uint32_t)m;
+      chain_tab[3 * at + 1] = first;
+      chain_tab[3 * at + 2] = nb;
+    } else {
+      const uint32_t n_full = nb / chain, rest = nb - n_full * chain;
+      if (n_full) {
+        const uint32_t at = atomicAdd(&n_len[chain], n_full);
+        for (uint32_t c = 0; c < n_full; ++c) {
+          chain_tab[3 * (at + c) + 0] = (uint32_t)m;
+          chain_tab[3 * (at + c) + 1] = first + c * chain;
+          chain_tab[3 * (at + c) + 2] = chain;
+        }
       }
-    }
-    if (rest) {
-      const uint32_t at = atomicAdd(&n_len[rest], 1u);
-      chain_tab[2 * at + 0] = first + n_full * chain;
-      chain_tab[2 * at + 1] = rest;
+      if (rest) {
+        const uint32_t at = atomicAdd(&n_len[rest], 1u);
+        chain_tab[3 * at + 0] = (uint32_t)m;
+        chain_tab[3 * at + 1] = first + n_full * chain;
+        chain_tab[3 * at + 2] = rest;
+      }
     }
     first += nb;
   }
@@ -158,7 +172,7 @@ static void launch_table(int n_mt, uint32_t batch_cap, uint32_t max_batches, Dev
                          const uint32_t* mt_off, uint32_t* batch_first, uint32_t* batch_tab,
                          ChainBuffers cb, hipStream_t s) {
   hipLaunchKernelGGL(batch_table_kernel, dim3(1), dim3(kBtThreads), 0, s, n_mt, batch_cap, cb.chain,
-                     max_batches, mt_off, dc, batch_first, cb.tab);
+                     cb.whole, max_batches, mt_off, dc, batch_first, cb.tab);
   const int row_blocks = (n_mt + (kOffThreads / 64) - 1) / (kOffThreads / 64);
   if (row_blocks > 0)
     hipLaunchKernelGGL(batch_rows_kernel, dim3(row_blocks), dim3(kOffThreads), 0, s, n_mt,

@@ -42,9 +42,9 @@ struct higs_ctx {
   uint64_t* status = nullptr;
   uint32_t max_tiles = 0;
   uint32_t *mt_off = nullptr, *batch_first = nullptr, *batch_tab = nullptr, *active = nullptr;
-  uint32_t* chain_tab = nullptr;  // raster work items (runs of batches of a macro-tile)
-  float* chain_T = nullptr;  // [kMaxRasterWorkers][32 tiles][64 px] transmittance products
-  float4* partials = nullptr;
+  uint32_t* chain_tab = nullptr;  // raster work items (batches of one macro-tile)
+  float4* chain_acc = nullptr;  // [kMaxRasterWorkers][32 tiles][64 px] items' running state
+  float4* partials = nullptr;   // (one element when the frames fold their partials in the raster)
   DeviceCounters* dc = nullptr;
   // segmented sort: per macro-tile counts, fill cursors, chunk and block tables
   uint16_t* seg_cm = nullptr;  // [n_mt][n_b] count matrix
@@ -53,6 +53,13 @@ struct higs_ctx {
   // adjoint buffers, allocated by the first higs_raster_backward
   float2* bwd_state = nullptr;  // [max_batches][32 tiles][64 px]: T before, suffix X
   float* dgeo = nullptr;        // [max_g][16] record gradients
+  float4* partials_bwd = nullptr;  // [max_batches][32][64]: partials the adjoint has a fused
+                                   //   frame rasterised again into
+  bool fused_frame = false;  // the last frame folded its partials in the raster
+  // float32 frames fold the partials in the raster unless fuse_merge is 0
+  bool fuses() const {
+    return params.raster_precision == HIGS_RASTER_FP32 && params.fuse_merge != 0;
+  }
   // the scene arrays of the last higs_project (re-read by the adjoint)
   const float *in_means = nullptr, *in_scales = nullptr, *in_quats = nullptr,
               *in_opac = nullptr, *in_sh = nullptr;
@@ -164,7 +171,7 @@ void free_events(higs_ctx* c) {
 
 void free_all(higs_ctx* c) {
   // buffers allocated on demand (debug read-back, the adjoint's state)
-  void* extra[] = {c->dbg_keys, c->dbg_vals, c->bwd_state, c->dgeo};
+  void* extra[] = {c->dbg_keys, c->dbg_vals, c->bwd_state, c->dgeo, c->partials_bwd};
   for (void* b : extra)
     if (b) (void)hipFree(b);
   if (!c->external) {
@@ -172,7 +179,7 @@ void free_all(higs_ctx* c) {
                     c->f_span, c->rec, c->block_sums, c->keys[0], c->keys[1], c->vals[0],
                     c->vals[1], c->hist, c->plan, c->status, c->mt_off, c->batch_first,
                     c->batch_tab, c->active, c->partials, c->dc, c->chain_tab,
-                    c->chain_T, c->seg_cm, c->seg_off,
+                    c->chain_acc, c->seg_cm, c->seg_off,
                     c->seg_tiles, c->seg_list, c->view_table};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
@@ -225,10 +232,10 @@ void for_each_buffer(higs_ctx* c, F&& f) {
   f(&c->mt_off, mt + 1);
   f(&c->batch_first, mt + 1);
   f(&c->batch_tab, 3 * B);
-  f(&c->chain_tab, 2 * B);
-  f(&c->chain_T, (size_t)kMaxRasterWorkers * kTilesPerMt * 64);
+  f(&c->chain_tab, 3 * (B + mt));
+  f(&c->chain_acc, (size_t)kMaxRasterWorkers * kTilesPerMt * 64);
   f(&c->active, B);
-  f(&c->partials, B * kTilesPerMt * 64);
+  f(&c->partials, c->fuses() ? 1 : B * kTilesPerMt * 64);
   f(&c->dc, (size_t)1);
   // segmented sort (single-view contexts only): the (macro-tile, partition
   // batch) count matrix and its scan, the tile sums, the tier lists
@@ -322,6 +329,7 @@ void higs_default_params(higs_params* p) {
   p->max_views = 1;
   p->use_graphs = 0;
   p->raster_chain = 64;
+  p->fuse_merge = 1;
 }
 
 const char* higs_error_string(int code) {
@@ -368,6 +376,7 @@ int check_params(const higs_params& p, int64_t max_gaussians, int64_t max_pairs,
   if ((int64_t)p.max_views * pad_blocks(max_gaussians) > (int64_t)0xffffffff) return HIGS_E_INVALID;
   if (p.use_graphs != 0 && p.use_graphs != 1) return HIGS_E_INVALID;
   if (p.raster_chain < 1 || p.raster_chain > kMaxChain) return HIGS_E_INVALID;
+  if (p.fuse_merge != 0 && p.fuse_merge != 1) return HIGS_E_INVALID;
   return HIGS_OK;
 }
 
@@ -819,7 +828,10 @@ int higs_batch(higs_ctx* c, void* stream) {
   const uint64_t* k2[2] = {c->keys[0], c->keys[1]};
   // chains apply to the float32 rasteriser; the other keeps one batch per item
   ChainBuffers cb;
-  cb.chain = c->params.raster_precision == HIGS_RASTER_FP32 ? (uint32_t)c->params.raster_chain : 1u;
+  cb.whole = c->fuses();
+  cb.chain = (!cb.whole && c->params.raster_precision == HIGS_RASTER_FP32)
+                 ? (uint32_t)c->params.raster_chain
+                 : 1u;
   cb.tab = c->chain_tab;
   int rc;
   {
@@ -847,14 +859,17 @@ int raster_frame(higs_ctx* c, hipStream_t s) {
   int rc;
   const bool half = c->params.raster_precision == HIGS_RASTER_FP16;
   const bool count = (c->debug_flags & HIGS_DEBUG_COUNT_EVALS) != 0;
+  const bool fused = c->fuses();
+  c->fused_frame = fused;
   {
     TimerScope ts(c, HIGS_TIMER_RASTER, s);
     if (half)
       rc = hip_err(launch_raster16(c->ca, c->pa, v2, c->rec, c->batch_tab, c->dc, c->partials,
                                    c->active, c->n_cus, count, s));
     else
-      rc = hip_err(launch_raster(c->ca, c->pa, v2, c->rec, c->batch_tab, c->chain_tab, c->dc,
-                                 c->partials, c->active, c->chain_T, c->n_cus, count, s));
+      rc = hip_err(launch_raster(c->ca, c->pa, c->views, v2, c->rec, c->batch_tab, c->chain_tab,
+                                 c->dc, c->partials, c->active, c->chain_acc, c->n_cus, count,
+                                 fused, s));
   }
   if (rc) return rc;
   {
@@ -862,7 +877,7 @@ int raster_frame(higs_ctx* c, hipStream_t s) {
     if (half)
       rc = hip_err(launch_merge16(c->ca, c->pa, c->views, c->batch_first, c->active, c->partials,
                                   c->dc, s));
-    else
+    else if (!fused)  // (fused: the raster wrote the images)
       rc = hip_err(launch_merge(c->ca, c->pa, c->views, c->batch_first, c->active, c->partials,
                                 c->dc, s));
   }
@@ -1082,9 +1097,23 @@ int higs_raster_backward(higs_ctx* c, const float* dL_dimage, const float* dL_dT
   hipStream_t s = (hipStream_t)stream;
   c->last_stream = s;
   const uint32_t* v2[2] = {c->vals[0], c->vals[1]};
+  float4* parts = c->partials;
+  if (c->fused_frame) {
+    // the frame folded its partials in the raster: rasterise it again (same
+    // work items, same partials) into a buffer of the adjoint's
+    if (!c->partials_bwd &&
+        dalloc(&c->partials_bwd, (size_t)c->max_batches * kTilesPerMt * 64) != HIGS_OK)
+      return HIGS_E_NOMEM;
+    parts = c->partials_bwd;
+    int rc = hip_err(launch_raster_rewind(c->dc, s));
+    if (rc) return rc;
+    rc = hip_err(launch_raster(c->ca, c->pa, c->views, v2, c->rec, c->batch_tab, c->chain_tab,
+                               c->dc, parts, c->active, c->chain_acc, c->n_cus, false, false, s));
+    if (rc) return rc;
+  }
   return hip_err(launch_backward(c->n, c->in_means, c->in_scales, c->in_quats, c->in_sh, c->ca,
                                  c->pa, v2, c->rec, c->f_cnt, c->batch_tab, c->batch_first,
-                                 c->active, c->partials, c->dc, dL_dimage, dL_dT, c->bwd_state,
+                                 c->active, parts, c->dc, dL_dimage, dL_dT, c->bwd_state,
                                  c->dgeo, dmeans, dscales, dquats, dopacities, dsh, c->n_cus, s));
 }
 
@@ -1223,9 +1252,11 @@ int higs_debug_copy(higs_ctx* c, int which, void* host_dst, size_t bytes) {
       return cp(c->batch_tab, bytes);
     case HIGS_DBG_ACTIVE:
       if (c->stage < 4 || bytes > nb * 4) return HIGS_E_INVALID;
+      if (c->fused_frame) return HIGS_E_STATE;
       return cp(c->active, bytes);
     case HIGS_DBG_PARTIALS:
       if (c->stage < 4 || bytes > nb * kTilesPerMt * 64 * 16) return HIGS_E_INVALID;
+      if (c->fused_frame) return HIGS_E_STATE;
       return cp(c->partials, bytes);
     default:
       return HIGS_E_INVALID;

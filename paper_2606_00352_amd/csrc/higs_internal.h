@@ -195,21 +195,28 @@ hipError_t launch_sort(int n_passes, int mt_bits, SortBuffers sb,
                        DeviceCounters* dc, int n_cus, hipStream_t s);
 
 // Raster work items: runs of up to `chain` consecutive batches of one
-// macro-tile; tab rows are (first batch, batches), longest runs first.
+// macro-tile, or (whole) every macro-tile with all its batches, empty ones
+// included; tab rows are (macro-tile, first batch, batches), longest first.
 struct ChainBuffers {
   uint32_t chain;
-  uint32_t* tab;    // [max_batches][2]
+  bool whole;
+  uint32_t* tab;    // [max_batches + macro-tiles][3]
 };
 
 hipError_t launch_batch(int n_mt, uint32_t batch_cap, uint32_t max_batches, const uint64_t* const* keys2,
                         DeviceCounters* dc, uint32_t* mt_off, uint32_t* batch_first,
                         uint32_t* batch_tab, ChainBuffers cb, hipStream_t s);
 
-hipError_t launch_raster(CamArgs cam, ParamArgs prm, const uint32_t* const* vals2,
+// fused: whole-macro-tile items fold their partials into the views' images
+// (acc: per workgroup 32 x 64 float4 running sums); otherwise partials and
+// active masks for the merge, and acc holds the items' products of T.
+hipError_t launch_raster(CamArgs cam, ParamArgs prm, const Views& views, const uint32_t* const* vals2,
                          const RasterRecord* rec, const uint32_t* batch_tab,
                          const uint32_t* chain_tab, DeviceCounters* dc, float4* partials,
-                         uint32_t* active, float* chain_T, int n_cus, bool count_evals,
+                         uint32_t* active, float4* acc, int n_cus, bool count_evals, bool fused,
                          hipStream_t s);
+// Resets the rasteriser's work counter (to rasterise a frame again).
+hipError_t launch_raster_rewind(DeviceCounters* dc, hipStream_t s);
 
 // Half-precision rasteriser and merge; the partials buffer then holds four
 // halves per pixel.

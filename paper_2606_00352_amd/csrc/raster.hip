@@ -1,8 +1,14 @@
 // Stage 4: macro-tile rasterisation (sec. 3.4, Algorithms 1 and 2) and the
 // post-blend merge of Eq. 1.
 //
-// raster_kernel: persistent; each workgroup (8 waves) claims (macro-tile,
-// batch) processing units from a device counter.  Per unit:
+// raster_kernel: persistent; each workgroup (8 waves) claims work items
+// from a device counter: consecutive (macro-tile, batch) processing units of
+// one macro-tile, taken in order.  Along an item it keeps per render tile the
+// merge's running state, and leaves a tile out of the later units once its
+// transmittance is below t_eps at every pixel.  Fused, an item holds all
+// batches of its macro-tile and writes the macro-tile's pixels itself (Eq. 1
+// folded as the merge folds it); otherwise each unit's partials go to memory
+// for merge_kernel.  Per unit:
 //   Phase 1 (load + inline visibility): wave w takes mini-batches k = w, w+8
 //     (64 gaussians each, one per lane), gathers each gaussian's 48-byte record
 //     by its sorted id, stores it in LDS in macro-tile-relative pixels with
@@ -16,8 +22,8 @@
 //     masks in depth order on the scalar unit and blends front to back in
 //     float32.  A pixel stops once T < t_eps; the wave leaves the tile once
 //     every pixel has stopped.  The partial (C, T) of every active tile is
-//     streamed out with non-temporal stores; the active-tile mask goes to a
-//     per-unit word.
+//     folded into the item's state or streamed out with non-temporal stores
+//     (the active-tile mask then goes to a per-unit word).
 // merge_kernel: one wave per render tile walks its macro-tile's batches in
 //   depth order, reads only active partials, accumulates
 //   C += T_acc C_b, T_acc *= T_b while T_acc >= t_eps and writes
@@ -29,22 +35,40 @@ namespace higs {
 constexpr int kRasterThreads = 512;
 constexpr int kRasterWaves = kRasterThreads / 64;
 
-template <bool kCountEvals>
+template <bool kCountEvals, bool kFused>
 __global__ void __launch_bounds__(kRasterThreads)
-raster_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ vals0,
+raster_kernel(CamArgs cam, ParamArgs prm, Views views, const uint32_t* __restrict__ vals0,
               const uint32_t* __restrict__ vals1, const RasterRecord* __restrict__ rec,
               const uint32_t* __restrict__ batch_tab, const uint32_t* __restrict__ chain_tab,
               DeviceCounters* __restrict__ dc, float4* __restrict__ partials,
-              uint32_t* __restrict__ active, float* __restrict__ chain_T) {
+              uint32_t* __restrict__ active, float4* __restrict__ acc) {
   __shared__ RasterLds L;
-  if (dc->overflow) return;  // the frame stops at a capacity overflow
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (dc->overflow) {  // the frame stops at a capacity overflow
+    if (kFused) {      // and no work items were made: the images say so
+      const float nan = __builtin_nanf("");
+      const size_t n_px = (size_t)cam.width * cam.height;
+      for (int v = 0; v < views.count; ++v) {
+        const ViewArgs& w = views.get(v);
+        for (size_t p = (size_t)blockIdx.x * kRasterThreads + tid; p < n_px;
+             p += (size_t)gridDim.x * kRasterThreads) {
+          w.image[3 * p + 0] = nan;
+          w.image[3 * p + 1] = nan;
+          w.image[3 * p + 2] = nan;
+          if (w.T) w.T[p] = nan;
+        }
+      }
+    }
+    return;
+  }
   const uint32_t* __restrict__ sorted = dc->sort_final ? vals1 : vals0;
   const uint32_t n_chains = dc->n_chains;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const float eps = prm.t_eps, amax = prm.alpha_max;
   const float pxo = (float)(lane & 7) + 0.5f, pyo = (float)(lane >> 3) + 0.5f;
-  // this workgroup's products of the batch transmittances along a chain
-  float* __restrict__ myT = chain_T + (size_t)blockIdx.x * kTilesPerMt * 64;
+  // this workgroup's running state along a work item, per tile and pixel:
+  // fused, the merge's (C, T_acc); otherwise the product of the batches' T
+  float4* __restrict__ my_acc = acc + (size_t)blockIdx.x * kTilesPerMt * 64;
+  float* __restrict__ my_T = reinterpret_cast<float*>(my_acc);
 
   uint64_t evals_all = 0;  // this wave's evaluations (the count-evals variant)
   for (;;) {
@@ -53,22 +77,26 @@ raster_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ vals0,
     __syncthreads();
     const uint32_t ch = L.unit;
     if (ch >= n_chains) break;
-    const uint32_t u0 = chain_tab[2 * ch], n_u = chain_tab[2 * ch + 1];
+    UnitInfo M;  // the item's macro-tile
+    M.mt = chain_tab[3 * ch];
+    const uint32_t u0 = chain_tab[3 * ch + 1], n_u = chain_tab[3 * ch + 2];
+    mt_place(cam, M);
+    // the render tiles inside the image
+    uint32_t inside = 0;
+    for (int r = 0; r < M.tiles_y; ++r) inside |= (0xffu >> (kMtTilesX - M.tiles_x)) << (r * kMtTilesX);
     for (uint32_t i = 0; i < n_u; ++i) {
       const uint32_t u = u0 + i;
       const UnitInfo I = unit_info(cam, batch_tab, u);
-      // the render tiles inside the image, and those the chain's earlier
-      // batches saturated (read after the barrier that ended the last unit)
-      uint32_t inside = 0;
-      for (int r = 0; r < I.tiles_y; ++r) inside |= (0xffu >> (kMtTilesX - I.tiles_x)) << (r * kMtTilesX);
+      // the tiles the item's earlier batches saturated (read after the
+      // barrier that ended the last unit)
       const uint32_t sat = (uint32_t)__ballot(lane < kTilesPerMt && L.tstate[lane & (kTilesPerMt - 1)] == 2u);
       if ((sat & inside) == inside) {  // the merge reads nothing of this unit
-        if (tid == 0) active[u] = 0u;
+        if (!kFused && tid == 0) active[u] = 0u;
         continue;
       }
       if (tid == 0) L.qnext = 0;
       const uint32_t act = stage_unit<kRasterWaves>(L, I, sorted, rec, lane, wave, sat);
-      if (tid == 0) active[u] = act;
+      if (!kFused && tid == 0) active[u] = act;
 
       // Phase 2: waves claim tiles
       for (;;) {
@@ -102,30 +130,61 @@ raster_kernel(CamArgs cam, ParamArgs prm, const uint32_t* __restrict__ vals0,
           if (__ballot(T >= eps) == 0) break;
         }
         if (kCountEvals) evals_all += evals;
-        v4f* dst = reinterpret_cast<v4f*>(partials + (((size_t)u * kTilesPerMt + t) * 64 + lane));
-        const v4f val = {cr, cg, cb, T};
-        __builtin_nontemporal_store(val, dst);
-        if (i + 1 < n_u) {
-          // the tile's product of T over the chain so far, in the order and
-          // the float32 arithmetic of the merge: with t_eps reached at every
-          // pixel, the merge (whose own product is never larger) has stopped
-          // reading this tile, and the chain's later batches leave it out.
-          // Only this wave writes the tile's state in this unit, and every
-          // lane stores the same word: no lane-0 branch in this loop, which
-          // would let the compiler split the wave around next_tile's
-          // readfirstlane
-          float* __restrict__ pt = myT + t * 64 + lane;
-          const uint32_t st = L.tstate[t];
-          const float prod = st == 0u ? T : *pt * T;
-          *pt = prod;
-          const bool done = __ballot(prod >= eps) == 0ull;
-          L.tstate[t] = done ? 2u : 1u;
+        // Only this wave writes the tile's state in this unit, and every lane
+        // stores the same word: no lane-0 branch in this loop, which would
+        // let the compiler split the wave around next_tile's readfirstlane.
+        const uint32_t st = L.tstate[t];
+        if (kFused) {
+          // the merge's step for this batch's partial (Eq. 1), its float32
+          // operations in its order; a tile without partial in a batch is the
+          // identity step, so leaving it out changes nothing
+          float4* __restrict__ pa = my_acc + t * 64 + lane;
+          float4 s = st == 0u ? make_float4(0.0f, 0.0f, 0.0f, 1.0f) : *pa;
+          if (s.w >= eps) {
+            s.x = fmaf(s.w, cr, s.x);
+            s.y = fmaf(s.w, cg, s.y);
+            s.z = fmaf(s.w, cb, s.z);
+            s.w = s.w * T;
+          }
+          *pa = s;
+          L.tstate[t] = __ballot(s.w >= eps) == 0ull ? 2u : 1u;
+        } else {
+          v4f* dst = reinterpret_cast<v4f*>(partials + (((size_t)u * kTilesPerMt + t) * 64 + lane));
+          const v4f val = {cr, cg, cb, T};
+          __builtin_nontemporal_store(val, dst);
+          if (i + 1 < n_u) {
+            // the tile's product of T over the item so far, in the order and
+            // the float32 arithmetic of the merge: with t_eps reached at
+            // every pixel, the merge (whose own product is never larger) has
+            // stopped reading this tile, and the item's later batches leave
+            // it out
+            float* __restrict__ pt = my_T + t * 64 + lane;
+            const float prod = st == 0u ? T : *pt * T;
+            *pt = prod;
+            L.tstate[t] = __ballot(prod >= eps) == 0ull ? 2u : 1u;
+          }
         }
       }
       __syncthreads();
     }
-    // a chain that ended on a left-out unit has not passed the barrier above:
-    // no wave may still read the tile states when the next chain resets them
+    if (kFused) {
+      // the item's pixels (all batches of its macro-tile folded): Eq. 1's
+      // C + T_acc * background and T_acc, as the merge writes them
+      const ViewArgs& w = views.get((int)(M.mt / (uint32_t)views.n_mt));
+      for (int t = wave; t < kTilesPerMt; t += kRasterWaves) {
+        const int x = M.x0 + (t & 7) * kTile + (lane & 7), y = M.y0 + (t >> 3) * kTile + (lane >> 3);
+        const float4 s = L.tstate[t] == 0u ? make_float4(0.0f, 0.0f, 0.0f, 1.0f) : my_acc[t * 64 + lane];
+        if (x < cam.width && y < cam.height) {
+          const size_t pix = (size_t)y * cam.width + x;
+          w.image[3 * pix + 0] = fmaf(s.w, w.bg[0], s.x);
+          w.image[3 * pix + 1] = fmaf(s.w, w.bg[1], s.y);
+          w.image[3 * pix + 2] = fmaf(s.w, w.bg[2], s.z);
+          if (w.T) w.T[pix] = s.w;
+        }
+      }
+    }
+    // an item that ended on a left-out unit has not passed the barrier above:
+    // no wave may still read the tile states when the next item resets them
     __syncthreads();
   }
   if (kCountEvals && lane == 0) atomicAdd(&dc->n_evals, (unsigned long long)evals_all);
@@ -172,9 +231,9 @@ merge_kernel(CamArgs cam, ParamArgs prm, Views views, const uint32_t* __restrict
         pn = load(b);
       }
       if (T >= eps) {
-        cr += T * p.x;
-        cg += T * p.y;
-        cb += T * p.z;
+        cr = fmaf(T, p.x, cr);
+        cg = fmaf(T, p.y, cg);
+        cb = fmaf(T, p.z, cb);
         T = T * p.w;
       }
       if (__ballot(T >= eps) == 0) {
@@ -194,9 +253,9 @@ merge_kernel(CamArgs cam, ParamArgs prm, Views views, const uint32_t* __restrict
     float* __restrict__ image = w.image;
     float* __restrict__ T_out = w.T;
     const size_t pix = (size_t)y * cam.width + x;
-    image[3 * pix + 0] = cr + T * w.bg[0];
-    image[3 * pix + 1] = cg + T * w.bg[1];
-    image[3 * pix + 2] = cb + T * w.bg[2];
+    image[3 * pix + 0] = fmaf(T, w.bg[0], cr);
+    image[3 * pix + 1] = fmaf(T, w.bg[1], cg);
+    image[3 * pix + 2] = fmaf(T, w.bg[2], cb);
     if (T_out) T_out[pix] = T;
   }
 }
@@ -208,7 +267,7 @@ static int g_raster_per_cu = 0;
 int raster_per_cu_config() {
   if (g_raster_per_cu == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, raster_kernel<false>, kRasterThreads, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, raster_kernel<false, true>, kRasterThreads, 0) !=
             hipSuccess ||
         nb < 1)
       nb = 1;
@@ -217,20 +276,29 @@ int raster_per_cu_config() {
   return g_raster_per_cu;
 }
 
-hipError_t launch_raster(CamArgs cam, ParamArgs prm, const uint32_t* const* vals2,
+hipError_t launch_raster(CamArgs cam, ParamArgs prm, const Views& views, const uint32_t* const* vals2,
                          const RasterRecord* rec, const uint32_t* batch_tab,
                          const uint32_t* chain_tab, DeviceCounters* dc, float4* partials,
-                         uint32_t* active, float* chain_T, int n_cus, bool count_evals,
+                         uint32_t* active, float4* acc, int n_cus, bool count_evals, bool fused,
                          hipStream_t s) {
   raster_per_cu_config();
-  // one chain scratch slice per workgroup of the grid
+  // one running-state slice per workgroup of the grid
   const int grid = min(n_cus * g_raster_per_cu, kMaxRasterWorkers);
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kRasterThreads), 0, s, cam, prm, views, vals2[0],
+                       vals2[1], rec, batch_tab, chain_tab, dc, partials, active, acc);
+  };
   if (count_evals)
-    hipLaunchKernelGGL(raster_kernel<true>, dim3(grid), dim3(kRasterThreads), 0, s, cam, prm,
-                       vals2[0], vals2[1], rec, batch_tab, chain_tab, dc, partials, active, chain_T);
+    fused ? go(raster_kernel<true, true>) : go(raster_kernel<true, false>);
   else
-    hipLaunchKernelGGL(raster_kernel<false>, dim3(grid), dim3(kRasterThreads), 0, s, cam, prm,
-                       vals2[0], vals2[1], rec, batch_tab, chain_tab, dc, partials, active, chain_T);
+    fused ? go(raster_kernel<false, true>) : go(raster_kernel<false, false>);
+  return hipGetLastError();
+}
+
+__global__ void raster_rewind_kernel(DeviceCounters* dc) { dc->raster_next = 0u; }
+
+hipError_t launch_raster_rewind(DeviceCounters* dc, hipStream_t s) {
+  hipLaunchKernelGGL(raster_rewind_kernel, dim3(1), dim3(1), 0, s, dc);
   return hipGetLastError();
 }
 

@@ -95,20 +95,25 @@ struct UnitInfo {
   int len, K, x0, y0, tiles_x, tiles_y;
 };
 
-__device__ __forceinline__ UnitInfo unit_info(const CamArgs& cam, const uint32_t* batch_tab,
-                                              uint32_t u) {
-  UnitInfo I;
-  I.mt = batch_tab[3 * u + 0];
-  I.start = batch_tab[3 * u + 1];
-  I.len = (int)batch_tab[3 * u + 2];
-  // a frame of several views numbers the macro-tiles of view v after those of
-  // views 0 .. v-1: the position in the image is the local number's
+// The macro-tile's pixel origin in its view and its render tiles inside the
+// image (a frame of several views numbers the macro-tiles of view v after
+// those of views 0 .. v-1: the position is the local number's).
+__device__ __forceinline__ void mt_place(const CamArgs& cam, UnitInfo& I) {
   const uint32_t mtl = I.mt % (uint32_t)(cam.n_mt_x * cam.n_mt_y);
   const int mtx = (int)(mtl % (uint32_t)cam.n_mt_x), mty = (int)(mtl / (uint32_t)cam.n_mt_x);
   I.x0 = mtx * kMtW;
   I.y0 = mty * kMtH;
   I.tiles_x = min(kMtTilesX, (cam.width - I.x0 + kTile - 1) / kTile);
   I.tiles_y = min(kMtTilesY, (cam.height - I.y0 + kTile - 1) / kTile);
+}
+
+__device__ __forceinline__ UnitInfo unit_info(const CamArgs& cam, const uint32_t* batch_tab,
+                                              uint32_t u) {
+  UnitInfo I;
+  I.mt = batch_tab[3 * u + 0];
+  I.start = batch_tab[3 * u + 1];
+  I.len = (int)batch_tab[3 * u + 2];
+  mt_place(cam, I);
   I.K = (I.len + 63) >> 6;
   return I;
 }

@@ -48,7 +48,7 @@ class Params(ctypes.Structure):
                 ("dilation", ctypes.c_float), ("sort_mode", ctypes.c_int32),
                 ("raster_precision", ctypes.c_int32), ("sh_format", ctypes.c_int32),
                 ("max_views", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
-                ("raster_chain", ctypes.c_int32)]
+                ("raster_chain", ctypes.c_int32), ("fuse_merge", ctypes.c_int32)]
 
 
 class CameraC(ctypes.Structure):
@@ -595,7 +595,9 @@ _RENDER_FN = None
 
 def render_differentiable(hctx: Context, means, scales, quats, opacities, sh, cam):
     """(image [H,W,3], T [H,W]) with gradients to every scene tensor (scales
-    linear, opacities in [0, 1], as higs_project takes them)."""
+    linear, opacities in [0, 1], as higs_project takes them).  A context made
+    with fuse_merge=0 keeps the partials the adjoint reads; with the default
+    the adjoint first rasterises the frame again."""
     global _RENDER_FN
     if _RENDER_FN is None:
         _RENDER_FN = _render_function()

@@ -82,7 +82,7 @@ class Frame:
 
 
 def run_frames(scene, cams, max_pairs, max_batches, sort_mode=1, batch_cap=1024, n_cus=2,
-               entry=0, uses=None, timeout=600, workdir=None, precision=0, sh_format=0, chain=64):
+               entry=0, uses=None, timeout=600, workdir=None, precision=0, sh_format=0, chain=64, fuse=1):
     """Renders `scene` (numpy arrays) for each camera; returns a list of Frame
     with rc, n_visible, n_pairs, n_batches, overflow, image, T, and (when the
     frame did not overflow) sorted keys/ids and the batch table."""
@@ -97,7 +97,7 @@ def run_frames(scene, cams, max_pairs, max_batches, sort_mode=1, batch_cap=1024,
         uses = uses or [n] * len(cams)
         with open(os.path.join(work, "job.txt"), "w") as f:
             f.write(f"{n} {max_pairs} {max_batches} {sort_mode} {batch_cap} {n_cus} {entry} {precision} "
-                    f"{sh_format} {chain}\n")
+                    f"{sh_format} {chain} {fuse}\n")
             for c, u in zip(cams, uses):
                 w = np.asarray(c.world_to_cam, np.float32).reshape(-1)
                 bg = getattr(c, "background", (0.0, 0.0, 0.0))

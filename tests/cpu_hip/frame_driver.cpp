@@ -4,7 +4,7 @@
 // table) into <out>.
 //
 // job.txt: one frame per line after a header line "n max_pairs max_batches
-// sort_mode batch_cap n_cus entry precision sh_format chain" (entry 0 = the stages one
+// sort_mode batch_cap n_cus entry precision sh_format chain fuse" (entry 0 = the stages one
 // by one on a context, 1 = the allocation-free entry point, 2 = every frame as
 // a view of one higs_render_views frame, 3 = higs_render with graph replay,
 // 4 = as 2 with graph replay, the frame recorded by a first call with the
@@ -132,9 +132,9 @@ int main(int argc, char** argv) {
   long long n, max_pairs, max_batches;
   int sort_mode, batch_cap, n_cus, entry;
   int precision = 0, sh_format = 0;
-  int chain = 8;
-  if (fscanf(jf, "%lld %lld %lld %d %d %d %d %d %d %d", &n, &max_pairs, &max_batches, &sort_mode,
-             &batch_cap, &n_cus, &entry, &precision, &sh_format, &chain) != 10)
+  int chain = 64, fuse = 1;
+  if (fscanf(jf, "%lld %lld %lld %d %d %d %d %d %d %d %d", &n, &max_pairs, &max_batches, &sort_mode,
+             &batch_cap, &n_cus, &entry, &precision, &sh_format, &chain, &fuse) != 11)
     return 2;
   std::vector<float> means = load(in + "/means", (size_t)n * 3);
   std::vector<float> scales = load(in + "/scales", (size_t)n * 3);
@@ -148,6 +148,7 @@ int main(int argc, char** argv) {
   p.raster_precision = precision;
   p.sh_format = sh_format;
   p.raster_chain = chain;
+  p.fuse_merge = fuse;
   // packed SH: compressed once by the library, written out for the tests
   std::vector<unsigned char> packed;
   if (sh_format == HIGS_SH_PACKED32) {

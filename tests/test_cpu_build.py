@@ -202,7 +202,9 @@ def test_raster_chains_skip_saturated_tiles(orc):
     """A raster work item of several batches of one macro-tile leaves out the
     render tiles whose product of transmittances over its earlier batches is
     below t_eps everywhere: the image and T are those of one batch per work
-    item, bit for bit, and of the oracle, with fewer evaluations."""
+    item, bit for bit, and of the oracle, with fewer evaluations.  Items of
+    whole macro-tiles that fold their partials themselves (no merge kernel)
+    give the same image and T as well."""
     from paper_2606_00352_amd import higs
     cpu = _cpu()
     sc, cam = _dense_scene(9000, 256, 128, 256.0, 21, 20, 10, 0.004)
@@ -210,18 +212,21 @@ def test_raster_chains_skip_saturated_tiles(orc):
     old = os.environ.get("HIGS_CPU_DEBUG")
     os.environ["HIGS_CPU_DEBUG"] = str(higs.DEBUG_COUNT_EVALS)
     try:
-        one = cpu.run_frames(sc, [cam], max_pairs=1 << 16, max_batches=256, batch_cap=256, chain=1)[0]
+        kw = dict(max_pairs=1 << 16, max_batches=256, batch_cap=256)
+        one = cpu.run_frames(sc, [cam], chain=1, fuse=0, **kw)[0]
         # runs of three (items of lengths 3, 2 and 1 in one list) and whole macro-tiles
-        three = cpu.run_frames(sc, [cam], max_pairs=1 << 16, max_batches=256, batch_cap=256, chain=3)[0]
-        many = cpu.run_frames(sc, [cam], max_pairs=1 << 16, max_batches=256, batch_cap=256, chain=64)[0]
+        three = cpu.run_frames(sc, [cam], chain=3, fuse=0, **kw)[0]
+        many = cpu.run_frames(sc, [cam], chain=64, fuse=0, **kw)[0]
+        fused = cpu.run_frames(sc, [cam], fuse=1, **kw)[0]
     finally:
         if old is None:
             del os.environ["HIGS_CPU_DEBUG"]
         else:
             os.environ["HIGS_CPU_DEBUG"] = old
-    assert one.rc == 0 and three.rc == 0 and many.rc == 0 and one.n_batches > 8
-    for r in (three, many):
+    assert one.rc == 0 and three.rc == 0 and many.rc == 0 and fused.rc == 0 and one.n_batches > 8
+    for r in (three, many, fused):
         assert np.array_equal(one.image, r.image) and np.array_equal(one.T, r.T)
+    assert fused.n_evaluations == many.n_evaluations
     assert 0 < many.n_evaluations <= three.n_evaluations <= one.n_evaluations
     assert many.n_evaluations < one.n_evaluations
     prm = orc.Params()

@@ -189,3 +189,37 @@ def test_1m_gaussians_1080p(orc):
     sc = scenes.clustered_scene(1_000_000, seed=4)
     cam = scenes.orbit_cameras(60, 101, 1920, 1080, 1100.0)[0]
     _check(orc, sc, cam)
+
+
+def test_adjoint_of_a_fused_frame():
+    """A default frame folds its partials in the raster and stores none: the
+    adjoint rasterises it again with partials.  Its gradients equal those of
+    a frame rendered with the merge kernel (fuse_merge = 0) up to the order of
+    the gradient atomics, and so do those of a second adjoint of the same
+    frame; the images are equal bit for bit."""
+    import torch
+    from paper_2606_00352_amd import higs
+    gc.need_gpu()
+    sc = scenes.clustered_scene(40_000, seed=31, n_clusters=8)
+    cam = scenes.orbit_cameras(3, 5, 320, 200, 220.0)[1]
+    W, V = _upstream(cam, 4)
+    t = higs.scene_tensors(sc)  # alive until both contexts are done with it
+    dW, dV = torch.from_numpy(W).cuda(), torch.from_numpy(V).cuda()
+    grads, imgs = [], []
+    for fuse in (1, 0):
+        ctx = higs.Context(sc.n, cam.width, cam.height, fuse_merge=fuse)
+        img, _ = higs.render(ctx, t, cam)
+        for _ in range(2 if fuse else 1):
+            outs = [torch.empty_like(x) for x in t]
+            ctx.raster_backward(dW, dV, *outs)
+            torch.cuda.synchronize()
+            grads.append([o.cpu().numpy() for o in outs])
+        assert ctx.counts().overflow == 0
+        imgs.append(img.cpu().numpy())
+        ctx.close()
+    assert np.array_equal(imgs[0], imgs[1])
+    ref = grads[2]
+    for got in grads[:2]:
+        for name, a, b in zip(NAMES, got, ref):
+            scale = max(float(np.abs(b).max()), 1e-30)
+            assert np.abs(a - b).max() <= 1e-5 * scale, name

@@ -44,8 +44,13 @@ def _full_check(orc, scene, cam, cap=1024, report=None, check_partials=True, sor
     cmax = float(fr.geo[fr.valid == 1, orc.G_R:orc.G_BL + 1].max()) if fr.valid.any() else 1.0
     gc.check_image(img, T, fr.image, fr.T, fr.amb, report, cmax)
     if check_partials and fr.batch_tab.shape[0]:
-        parts = ctx.partials()
-        act = ctx.active()
+        # the partials of a frame with the merge kernel (fuse_merge = 0), whose
+        # image and T equal the fused frame's bit for bit
+        pctx, pimg, pT = gc.gpu_frame(scene, cam, batch_cap=cap, sort_mode=sort_mode, debug=debug,
+                                      fuse_merge=0)
+        assert np.array_equal(pimg, img) and np.array_equal(pT, T)
+        parts = pctx.partials()
+        act = pctx.active()
         rng = np.random.default_rng(0)
         pick = rng.choice(fr.batch_tab.shape[0], size=min(12, fr.batch_tab.shape[0]), replace=False)
         nmx = (cam.width + 63) // 64

@@ -25,16 +25,19 @@ def test_context_footprint_counts_every_array():
     nchunk = (nblk + 255) // 256          # scan chunks of 256 projection blocks
     want = (G * (9 * 4 + 48) + 2 * nblk * 4 + 2 * nchunk * 4 + P * 24 + 8 * radix * 4 + (8 + 8 * radix) * 4
             + tiles * radix * 8
-            + 2 * (n_mt + 1) * 4 + B * 16 + B * 32 * 64 * 16 + B * 8   # + raster work items
-            + 1024 * 32 * 64 * 4)                                        # chain products, 1,024 workers
+            + 2 * (n_mt + 1) * 4 + B * 16                    # macro-tile offsets, batch table, active
+            + (B + n_mt) * 12                                # raster work items
+            + 1024 * 32 * 64 * 16)                           # items' running state, 1,024 workers
     got = higs.ctx_footprint(G, P, B, W, H)
-    assert 0 < got - want <= 1024         # plus the frame counters and the view table
+    assert 0 < got - want <= 1280         # plus the frame counters, the view table, a partial
     assert higs.ctx_footprint(G, 2 * P, B, W, H) > got
-    assert higs.ctx_footprint(G, P, 2 * B, W, H) - got == B * (16 + 32 * 64 * 16 + 8)
+    assert higs.ctx_footprint(G, P, 2 * B, W, H) - got == B * (16 + 12)
+    # partials and the merge: 16 bytes per pixel of every (batch, tile)
+    assert higs.ctx_footprint(G, P, B, W, H, fuse_merge=0) - got == B * 32 * 64 * 16 - 16
     assert higs.ctx_footprint(0, P, B, W, H) == higs.E_INVALID
     # four views per frame: four ranges of gaussians and of macro-tiles
     four = higs.ctx_footprint(G, P, B, W, H, max_views=4)
-    grow = 3 * (G * (9 * 4 + 48) + 2 * nblk * 4 + 2 * n_mt * 4)
+    grow = 3 * (G * (9 * 4 + 48) + 2 * nblk * 4 + 2 * n_mt * 4 + n_mt * 12)
     assert 0 < four - got - grow <= 3 * 256
 
 
