@@ -1,7 +1,7 @@
 // Stage 4: macro-tile rasterisation (sec. 3.4, Algorithms 1 and 2) and the
 // post-blend merge of Eq. 1.
 //
-// raster_kernel: persistent; each workgroup (8 waves) claims work items
+// raster_kernel: persistent; each workgroup (16 waves) claims work items
 // from a device counter: consecutive (macro-tile, batch) processing units of
 // one macro-tile, taken in order.  Along an item it keeps per render tile the
 // merge's running state, and leaves a tile out of the later units once its
@@ -9,7 +9,7 @@
 // batches of its macro-tile and writes the macro-tile's pixels itself (Eq. 1
 // folded as the merge folds it); otherwise each unit's partials go to memory
 // for merge_kernel.  Per unit:
-//   Phase 1 (load + inline visibility): wave w takes mini-batches k = w, w+8
+//   Phase 1 (load + inline visibility): wave w takes mini-batch k = w
 //     (64 gaussians each, one per lane), gathers each gaussian's 48-byte record
 //     by its sorted id, stores it in LDS in macro-tile-relative pixels with
 //     the Cholesky factors prescaled by sqrt(log2(e)/2) (so exp(-q/2) becomes
@@ -32,11 +32,15 @@
 
 namespace higs {
 
-constexpr int kRasterThreads = 512;
+// 16 waves per workgroup and two workgroups per CU (the LDS holds two; 64
+// VGPRs give the CU's 32 wave slots): a work item's tiles spread over twice
+// the waves of an 8-wave workgroup, three of which shared a CU before (1080p
+// raster 0.442 -> 0.387 ms: the frame waits on its heaviest items)
+constexpr int kRasterThreads = 1024;
 constexpr int kRasterWaves = kRasterThreads / 64;
 
 template <bool kCountEvals, bool kFused>
-__global__ void __launch_bounds__(kRasterThreads)
+__global__ void __launch_bounds__(kRasterThreads) __attribute__((amdgpu_waves_per_eu(8)))
 raster_kernel(CamArgs cam, ParamArgs prm, Views views, const uint32_t* __restrict__ vals0,
               const uint32_t* __restrict__ vals1, const RasterRecord* __restrict__ rec,
               const uint32_t* __restrict__ batch_tab, const uint32_t* __restrict__ chain_tab,
