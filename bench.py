@@ -58,14 +58,14 @@ COPY_CALIBRATION_BYTES = 1 << 30
 MEASURED_TRAFFIC = {
     # profiles/frame_1080p_5p8m_hbm_traffic.md (sort: histogram + plan + every
     # onesweep dispatch of a frame)
-    "raster": {"src_sha256": "c169c00f743cac3d25ff9546d8d3b8b0088424025eacc459da86346e7ee7c255",
-              "bytes_per_launch": 756500000},
-    "project": {"src_sha256": "114e4896592950c5b77f6cf5ad370dcdcb84d2e6bbb144933097b012bc3d6273",
+    "raster": {"src_sha256": "c32e47e80795f15311c28dd6fb70d71b6b0e98591da2bb20ab6e5650f488e997",
+              "bytes_per_launch": 757900000},
+    "project": {"src_sha256": "67522db790e7b471aed0f609ec544fb0c0d8fccb16aa0910587f93ca4d512ff6",
                "bytes_per_launch": 1714600000},
-    "fill": {"src_sha256": "7cee7960649929cb46d4a693074549546c05d393ddc0924fd483f4806551217e",
+    "fill": {"src_sha256": "1ead27d27351a98af1fb50ba28ecf0e07dd8bdfa8310c3bb6643c708e4eadf70",
             "bytes_per_launch": 134900000},
-    "sort": {"src_sha256": "c71ad7dc51ac2e8b1de9929e10927334857ff8aa5bbdfc82126ee6063bfc77a8",
-            "bytes_per_launch": 923000000},
+    "sort": {"src_sha256": "14d75baf2dc8209b5141d155b0e8298f56c251bc7325804af4d9d41cb4a59a1b",
+            "bytes_per_launch": 927300000},
 }
 # the sources each figure depends on (the shared header holds the kernels' shapes)
 KERNEL_SOURCES = {"project": ("project.hip", "predicate.h", "higs_internal.h"),

@@ -98,13 +98,13 @@ typedef struct {
                            of the earlier batches' transmittances is below t_eps at all 64 of
                            its pixels, where the merge of Eq. 1 stops reading; 1: every
                            (macro-tile, batch) unit is rasterised in full */
-  int32_t fuse_merge;   /* 1 (default): a float32 raster work item takes all batches of one
+  int32_t fuse_merge;   /* 1 (default): a raster work item takes all batches of one
                            macro-tile and folds their partials into its pixels itself, by
                            Eq. 1 in the merge's order and arithmetic (the same image and T,
-                           bit for bit); no partials are stored, no merge kernel runs, and
-                           raster_chain is not used.  0: the partials and the merge kernel,
-                           which higs_raster_backward reads (with 1 it first rasterises the
-                           frame again with partials) */
+                           bit for bit, in either raster_precision); no partials are stored,
+                           no merge kernel runs, and raster_chain is not used.  0: the
+                           partials and the merge kernel, which higs_raster_backward reads
+                           (with 1 it first rasterises the frame again with partials) */
 } higs_params;
 
 #define HIGS_MAX_VIEWS 64

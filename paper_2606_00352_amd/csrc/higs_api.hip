@@ -56,10 +56,8 @@ struct higs_ctx {
   float4* partials_bwd = nullptr;  // [max_batches][32][64]: partials the adjoint has a fused
                                    //   frame rasterised again into
   bool fused_frame = false;  // the last frame folded its partials in the raster
-  // float32 frames fold the partials in the raster unless fuse_merge is 0
-  bool fuses() const {
-    return params.raster_precision == HIGS_RASTER_FP32 && params.fuse_merge != 0;
-  }
+  // frames fold the partials in the raster unless fuse_merge is 0
+  bool fuses() const { return params.fuse_merge != 0; }
   // the scene arrays of the last higs_project (re-read by the adjoint)
   const float *in_means = nullptr, *in_scales = nullptr, *in_quats = nullptr,
               *in_opac = nullptr, *in_sh = nullptr;
@@ -863,7 +861,10 @@ int raster_frame(higs_ctx* c, hipStream_t s) {
   c->fused_frame = fused;
   {
     TimerScope ts(c, HIGS_TIMER_RASTER, s);
-    if (half)
+    if (half && fused)
+      rc = hip_err(launch_raster16_fused(c->ca, c->pa, c->views, v2, c->rec, c->batch_tab,
+                                         c->chain_tab, c->dc, c->chain_acc, c->n_cus, count, s));
+    else if (half)
       rc = hip_err(launch_raster16(c->ca, c->pa, v2, c->rec, c->batch_tab, c->dc, c->partials,
                                    c->active, c->n_cus, count, s));
     else
@@ -874,10 +875,12 @@ int raster_frame(higs_ctx* c, hipStream_t s) {
   if (rc) return rc;
   {
     TimerScope ts(c, HIGS_TIMER_MERGE, s);
-    if (half)
+    if (fused) {
+      // the raster wrote the images
+    } else if (half)
       rc = hip_err(launch_merge16(c->ca, c->pa, c->views, c->batch_first, c->active, c->partials,
                                   c->dc, s));
-    else if (!fused)  // (fused: the raster wrote the images)
+    else
       rc = hip_err(launch_merge(c->ca, c->pa, c->views, c->batch_first, c->active, c->partials,
                                 c->dc, s));
   }

@@ -220,6 +220,12 @@ hipError_t launch_raster_rewind(DeviceCounters* dc, hipStream_t s);
 
 // Half-precision rasteriser and merge; the partials buffer then holds four
 // halves per pixel.
+// Half precision, fused (whole-macro-tile work items; acc as launch_raster's).
+hipError_t launch_raster16_fused(CamArgs cam, ParamArgs prm, const Views& views,
+                                 const uint32_t* const* vals2, const RasterRecord* rec,
+                                 const uint32_t* batch_tab, const uint32_t* chain_tab,
+                                 DeviceCounters* dc, float4* acc, int n_cus, bool count_evals,
+                                 hipStream_t s);
 hipError_t launch_raster16(CamArgs cam, ParamArgs prm, const uint32_t* const* vals2,
                            const RasterRecord* rec, const uint32_t* batch_tab, DeviceCounters* dc,
                            void* partials, uint32_t* active, int n_cus, bool count_evals,

@@ -92,6 +92,9 @@ def test_half_precision_raster(orc):
     sc, cams = scenes.config0()
     cam = cams[0]
     fr = cpu.run_frames(sc, [cam], max_pairs=1 << 17, max_batches=1 << 12, precision=1)[0]
+    # the partials merged by the merge kernel instead of folded in the raster
+    frm = cpu.run_frames(sc, [cam], max_pairs=1 << 17, max_batches=1 << 12, precision=1, fuse=0)[0]
+    assert np.array_equal(fr.image, frm.image) and np.array_equal(fr.T, frm.T)
     o = orc.frame(sc, cam)
     want = (o.sorted_mt.astype(np.uint64) << np.uint64(32)) | o.sorted_key.astype(np.uint64)
     assert np.array_equal(fr.keys, want) and np.array_equal(fr.ids, o.sorted_gid.astype(np.uint32))

@@ -73,6 +73,9 @@ def test_half_precision_raster(orc, which):
     t = higs.scene_tensors(sc)
     c32, img32, T32 = _render(t, cam, sc.n)
     c16, img16, T16 = _render(t, cam, sc.n, raster_precision=higs.RASTER_FP16)
+    # the half-precision partials merged by the merge kernel: the same image and T
+    _, img16m, T16m = _render(t, cam, sc.n, raster_precision=higs.RASTER_FP16, fuse_merge=0)
+    assert np.array_equal(img16m, img16) and np.array_equal(T16m, T16)
     k32, v32 = c32.sorted_pairs()
     k16, v16 = c16.sorted_pairs()
     assert np.array_equal(k32, k16) and np.array_equal(v32, v16)
