@@ -211,17 +211,13 @@ project_kernel(Views views, CamArgs shape, ParamArgs prm, float* __restrict__ f_
   uint32_t cnt = 0;
   uint32_t kmin = 0xffffffffu, kmax = 0u;
   // degree 3 with a 16-byte aligned sh array: the 48 coefficients (192
-  // bytes) are loaded before the geometry, so that the loads overlap its
-  // arithmetic; packed SH: the 32 bytes of the gaussian and, in LDS, the 48
-  // scales of the header
+  // bytes) in twelve 16-byte loads once the gaussian is known to be visible
+  // (not held across the geometry: 94 VGPRs, five waves per SIMD, whose
+  // interleaving hides the loads); packed SH: the 32 bytes of the gaussian
+  // and, in LDS, the 48 scales of the header
   float4 shv[12];
   uint32_t shw[8];
   const bool early = !sh_packed && sh_vec4 && prm.sh_degree == 3 && i < n;
-  if (early) {
-    const float4* src = reinterpret_cast<const float4*>(sh + 48 * i);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) shv[k] = src[k];
-  }
   if (sh_packed) {
     if (threadIdx.x < kShComps) sh_scale[threadIdx.x] = sh[threadIdx.x];
     if (i < n) {
@@ -281,6 +277,11 @@ project_kernel(Views views, CamArgs shape, ParamArgs prm, float* __restrict__ f_
         if (sh_packed) {
           rgb = sh_colour([&](int k) { return sh_unpack(shw, sh_scale, k); }, 3, dx, dy, dz);
         } else if (early) {
+          {
+            const float4* src = reinterpret_cast<const float4*>(sh + 48 * i);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) shv[k] = src[k];
+          }
           const float* c = reinterpret_cast<const float*>(shv);
           rgb = sh_colour([&](int k) { return make_float3(c[3 * k], c[3 * k + 1], c[3 * k + 2]); },
                           3, dx, dy, dz);
