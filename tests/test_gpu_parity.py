@@ -336,3 +336,50 @@ def test_two_array_pairs(orc, make):
     (k1, v1), b1, i1, t1 = out[1]
     assert np.array_equal(k0, k1) and np.array_equal(v0, v1) and np.array_equal(b0, b1)
     assert np.array_equal(i0, i1) and np.array_equal(t0, t1)
+
+
+def test_work_item_forms_give_one_frame(orc):
+    """The raster's work items of 1, 2, 7 and 64 batches of a macro-tile with
+    stored partials and the merge kernel, and whole macro-tiles folding their
+    partials (the default), render the same image and T bit for bit; an item
+    that knows all earlier batches of its macro-tile evaluates no more
+    pixel-gaussian pairs than one that knows fewer, and the frame matches the
+    oracle (a dense, saturating scene: tiles fall below t_eps within a few
+    batches)."""
+    import torch
+    from paper_2606_00352_amd import higs
+    gc.need_gpu()
+    # 30,000 gaussians of opacity 0.9 in front of a 384 x 192 image: by the
+    # oracle's count half of the per-batch evaluations lie in tiles the merge
+    # no longer reads
+    n = 30_000
+    sc = scenes.uniform_scene(n, seed=43)
+    rng = np.random.default_rng(43)
+    z = rng.uniform(2, 6, n).astype(np.float32)
+    sc.means[:, 0] = rng.uniform(-150, 150, n) * z / 384.0
+    sc.means[:, 1] = rng.uniform(-75, 75, n) * z / 384.0
+    sc.means[:, 2] = z
+    sc.scales[:] = 0.02
+    sc.opacities[:] = 0.9
+    cam = scenes.camera_at_origin(384, 192, 384.0)
+    t = higs.scene_tensors(sc)
+    runs = []
+    for params in ({"fuse_merge": 0, "raster_chain": 1}, {"fuse_merge": 0, "raster_chain": 2},
+                   {"fuse_merge": 0, "raster_chain": 7}, {"fuse_merge": 0, "raster_chain": 64}, {}):
+        ctx = higs.Context(sc.n, cam.width, cam.height, max_pairs=16 * sc.n, batch_cap=256, **params)
+        ctx.set_debug(higs.DEBUG_COUNT_EVALS)
+        img, T = higs.render(ctx, t, cam)
+        torch.cuda.synchronize()
+        c = ctx.counts()
+        assert c.overflow == 0 and c.n_batches > 40
+        runs.append((img.cpu().numpy(), T.cpu().numpy(), int(c.n_evaluations)))
+        ctx.close()
+    for img, T, _ in runs[1:]:
+        assert np.array_equal(img, runs[0][0]) and np.array_equal(T, runs[0][1])
+    ev = [r[2] for r in runs]
+    assert ev[0] >= max(ev[1], ev[2]) and min(ev[1], ev[2]) >= ev[3] == ev[4] > 0, ev
+    assert ev[3] < 0.75 * ev[0], ev
+    prm = gc.oracle_params(orc, batch_cap=256)
+    fr = orc.frame(sc, cam, prm)
+    cmax = float(fr.geo[fr.valid == 1, orc.G_R:orc.G_BL + 1].max())
+    gc.check_image(runs[-1][0], runs[-1][1], fr.image, fr.T, fr.amb, {}, cmax)
