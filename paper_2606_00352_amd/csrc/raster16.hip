@@ -312,7 +312,8 @@ raster16_fused_kernel(CamArgs cam, ParamArgs prm, Views views, const uint32_t* _
       }
       __syncthreads();
       // queue of tile pairs (tile t with t + 8) holding any gaussian, but
-      // not those whose two tiles are both below t_eps
+      // not those whose two tiles are both below t_eps or outside the image
+      const uint32_t done = sat | ~inside;
       if (wave == 0) {
         uint64_t hit = 0;
         if (lane < kTilesPerMt)
@@ -321,7 +322,7 @@ raster16_fused_kernel(CamArgs cam, ParamArgs prm, Views views, const uint32_t* _
         const int p = lane & (kPairs - 1);
         const int t0 = (p >> 3) * 16 + (p & 7);
         const bool want = lane < kPairs && (((has >> t0) | (has >> (t0 + 8))) & 1u) &&
-                          !((sat >> t0) & (sat >> (t0 + 8)) & 1u);
+                          !((done >> t0) & (done >> (t0 + 8)) & 1u);
         const uint64_t pm = __ballot(want);
         if (want) L.pqueue[__popcll(pm & ((1ull << lane) - 1ull))] = (uint32_t)p;
         if (lane == 0) L.qcount = (uint32_t)__popcll(pm);
