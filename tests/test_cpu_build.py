@@ -22,6 +22,32 @@ def _cpu():
     return cpu_build
 
 
+@pytest.mark.parametrize("sort_mode", [0, 1], ids=["segmented", "onesweep"])
+def test_lists_of_many_bands_match_the_oracle(orc, sort_mode):
+    """Gaussians whose macro-tile lists span one to six bands: lists of one
+    or two bands go through the span word, longer ones through the predicate
+    again in the emission; the sorted pairs and batches equal the oracle's bit
+    for bit in both sort modes."""
+    cpu = _cpu()
+    sc, cam = _dense_scene(2500, 320, 256, 300.0, 51, 150, 120, 0.0)
+    rng = np.random.default_rng(51)
+    sc.scales[:] = rng.uniform(0.005, 0.2, (sc.n, 3)).astype(np.float32)
+    fr = cpu.run_frames(sc, [cam], max_pairs=1 << 17, max_batches=4096, sort_mode=sort_mode)[0]
+    o = orc.frame(sc, cam)
+    bands = {}
+    nx = (cam.width + 63) // 64
+    for m, g in zip(o.sorted_mt.tolist(), o.sorted_gid.tolist()):
+        lo, hi = bands.get(g, (1 << 30, -1))
+        bands[g] = (min(lo, m // nx), max(hi, m // nx))
+    spans = np.bincount([hi - lo + 1 for lo, hi in bands.values()])
+    assert spans[3:5].sum() >= 50 and spans[5:].sum() >= 5, spans
+    assert fr.rc == 0 and fr.overflow == 0
+    want = (o.sorted_mt.astype(np.uint64) << np.uint64(32)) | o.sorted_key.astype(np.uint64)
+    assert np.array_equal(fr.keys, want)
+    assert np.array_equal(fr.ids, o.sorted_gid.astype(np.uint32))
+    assert np.array_equal(fr.batches.astype(np.int64), o.batch_tab.astype(np.int64))
+
+
 def test_small_frame_matches_the_oracle(orc):
     """Pairs, sort order and batches bit-exact, image within the tolerance."""
     cpu = _cpu()
