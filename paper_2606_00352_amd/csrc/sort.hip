@@ -93,15 +93,22 @@ sort_plan_kernel(const uint32_t* __restrict__ hist, DeviceCounters* __restrict__
   const uint32_t n = dc->n_pairs;
   const int np = (mt_bits + (int)depth_bits(dc->key_min, dc->key_max) + kRadixBits - 1) / kRadixBits;
   const int d = threadIdx.x, lane = d & 63, wave = d >> 6;
+  // this digit's count in every pass, loaded together (one round trip)
+  uint32_t cnt[kMaxPasses];
+#pragma unroll
+  for (int p = 0; p < kMaxPasses; ++p) cnt[p] = p < n_passes ? hist[p * kRadix + d] : 0u;
   // a pass above the key width, or one whose digit every key shares, is skipped
   uint32_t skip = 0;
-  for (int p = 0; p < n_passes; ++p)
-    if (__syncthreads_or(hist[p * kRadix + d] == n) || p >= np) skip |= 1u << p;
+#pragma unroll
+  for (int p = 0; p < kMaxPasses; ++p)
+    if (p < n_passes && (__syncthreads_or(cnt[p] == n) || p >= np)) skip |= 1u << p;
   const uint32_t all = (1u << n_passes) - 1u;
   if (dc->id_shift && skip == all) skip &= ~1u;
   uint32_t cur = 0, moved = 0;
-  for (int p = 0; p < n_passes; ++p) {
-    const uint32_t c = hist[p * kRadix + d];
+#pragma unroll
+  for (int p = 0; p < kMaxPasses; ++p) {
+    if (p >= n_passes) break;
+    const uint32_t c = cnt[p];
     const int trivial = (skip >> p) & 1u;
     // exclusive scan of the digit counts
     uint32_t v = c;
