@@ -222,13 +222,15 @@ merge16_kernel(CamArgs cam, ParamArgs prm, Views views, const uint32_t* __restri
   }
 }
 
-// The fused form (fuse_merge = 1): persistent workgroups of 16 waves, two per
-// CU, take work items of whole macro-tiles as the float32 kernel does, stage
+// The fused form (fuse_merge = 1): persistent workgroups of 12 waves, two per
+// CU (80 VGPRs: the blend loop keeps its constants in registers; 16 waves at
+// 64 VGPRs measured 2% slower), take work items of whole macro-tiles as the
+// float32 kernel does, stage
 // each batch as above, and fold each tile pair's half-precision partials into
 // the item's float32 (C, T_acc) per pixel with merge16's operations in its
 // order, leaving out a pair once both tiles are below t_eps at every pixel;
 // at the item's end they write the macro-tile's pixels.
-constexpr int kR16FThreads = 1024;
+constexpr int kR16FThreads = 768;
 constexpr int kR16FWaves = kR16FThreads / 64;
 
 struct Raster16FLds {
@@ -237,7 +239,7 @@ struct Raster16FLds {
 };
 
 template <bool kCountEvals>
-__global__ void __launch_bounds__(kR16FThreads) __attribute__((amdgpu_waves_per_eu(8)))
+__global__ void __launch_bounds__(kR16FThreads) __attribute__((amdgpu_waves_per_eu(6)))
 raster16_fused_kernel(CamArgs cam, ParamArgs prm, Views views, const uint32_t* __restrict__ vals0,
                       const uint32_t* __restrict__ vals1, const RasterRecord* __restrict__ rec,
                       const uint32_t* __restrict__ batch_tab, const uint32_t* __restrict__ chain_tab,
