@@ -21,7 +21,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRCS = [os.path.join(_HERE, f) for f in ("higs_oracle.c", "higs_oracle_grad.c", "higs_oracle.h")]
-_LIB = os.path.join(_HERE, "liboracle.so")
+# HIGS_ORACLE_SANITIZE=1: a separate build under AddressSanitizer and
+# UndefinedBehaviorSanitizer (for a process that preloads their runtimes)
+_SANITIZE = os.environ.get("HIGS_ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
 
 TILE = 8
 MT_W, MT_H = 64, 32
@@ -40,8 +43,10 @@ def build(force: bool = False) -> str:
     """Compiles the oracle with gcc (double precision, no contraction)."""
     if force or not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(s) for s in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-               "-fPIC", "-shared", "-o", tmp] + [s for s in _SRCS if s.endswith(".c")] + ["-lm"]
+        san = (["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                "-fno-sanitize-recover=undefined"] if _SANITIZE else ["-O2"])
+        cmd = ["gcc"] + san + ["-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                               "-fPIC", "-shared", "-o", tmp] + [s for s in _SRCS if s.endswith(".c")] + ["-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)
     return _LIB
