@@ -28,7 +28,7 @@ DRIVER = os.path.join(BUILD, "frame_driver")
 CXX = os.environ.get("CPUHIP_CXX", "/opt/rocm/lib/llvm/bin/clang++")
 FLAGS = ["-std=c++20", "-O1", "-g", "-fno-omit-frame-pointer", "-ffp-contract=off",
          "-Wno-unknown-attributes", "-I", HERE]
-SAN = ["-fsanitize=address"]
+SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
 
 
 def available() -> bool:
